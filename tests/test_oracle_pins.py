@@ -1,0 +1,401 @@
+"""Pins of the FP64 oracle to facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints for its worked examples (tests/golden), Boolean truth tables,
+brute force over all 2^n assignments, the multilinear-expectation identity,
+the exact flip identity of the gradient, automatic differentiation by torch,
+and textbook optimizer routines from torch.optim.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_28796_amd import inputs as I
+
+
+def _cnf(clauses, n=None):
+    return I.from_clauses(clauses, n=n)
+
+
+def _bool_unsat(clauses, assign):
+    """Number of clauses with no true literal (DIMACS literals, 0/1 assign)."""
+    cnt = 0
+    for c in clauses:
+        if not any((assign[abs(l) - 1] == 1) if l > 0 else (assign[abs(l) - 1] == 0) for l in c):
+            cnt += 1
+    return cnt
+
+
+def _random_clauses(rng, n, m, kmin=1, kmax=5, distinct=True, allow_empty=False):
+    out = []
+    for _ in range(m):
+        k = int(rng.integers(0 if allow_empty else kmin, kmax + 1))
+        k = min(k, n) if distinct else k
+        vs = rng.choice(n, size=k, replace=False) if distinct else rng.integers(0, n, size=k)
+        out.append([int(v + 1) * (1 if rng.random() < 0.5 else -1) for v in vs])
+    return out
+
+
+# --- Eq. (1): the polynomial Boolean operations --------------------------------
+
+def test_eq1_or_not_and_polynomials():
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        x, y = rng.random(2)
+        xr = np.array([x, y])
+        # clause (x OR y): C = 1 - U must equal the OR polynomial x + y - x*y
+        C = 1.0 - oracle.clause_U([0, 2], xr)
+        assert C == pytest.approx(x + y - x * y, abs=1e-15)
+        # clause (NOT x): C = 1 - x  (negation rule)
+        assert 1.0 - oracle.clause_U([1], xr) == pytest.approx(1.0 - x, abs=1e-15)
+        # De Morgan: NOT(NOT x OR NOT y) = x AND y, whose polynomial is x*y;
+        # the clause (NOT x OR NOT y) has U = 1 - C = NOT(C)
+        assert oracle.clause_U([1, 3], xr) == pytest.approx(x * y, abs=1e-15)
+
+
+def test_eq1_truth_tables_at_01_points():
+    for a, b in itertools.product([0.0, 1.0], repeat=2):
+        xr = np.array([a, b])
+        assert 1.0 - oracle.clause_U([0, 2], xr) == float(bool(a) or bool(b))
+        assert oracle.clause_U([1, 3], xr) == float(bool(a) and bool(b))
+        assert 1.0 - oracle.clause_U([1], xr) == float(not bool(a))
+
+
+# --- Eq. (2): clause value at 0/1 points is exactly satisfaction --------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_eq2_brute_force_all_assignments(seed):
+    rng = np.random.default_rng(seed)
+    n = 10
+    clauses = _random_clauses(rng, n, 40, 1, 6)
+    clauses.append([3, 3, -5])        # repeated literal
+    clauses.append([4, -4])           # tautology
+    cnf = _cnf(clauses, n)
+    X = np.array(list(itertools.product([0.0, 1.0], repeat=n)))  # [2^n, n]
+    lo = oracle.loss(cnf, X)[0]
+    us = oracle.unsat(cnf, X)[0]
+    for i, row in enumerate(X):
+        want = _bool_unsat(clauses, row.astype(int))
+        assert lo[i] == float(want)
+        assert us[i] == want
+        assert (lo[i] == 0.0) == (want == 0)
+
+
+def test_empty_clause_always_unsat():
+    cnf = _cnf([[1, 2], []], 2)
+    X = np.array(list(itertools.product([0.0, 1.0], repeat=2)) + [[0.3, 0.6]])
+    lo = oracle.loss(cnf, X)[0]
+    us = oracle.unsat(cnf, X)[0]
+    assert np.all(us >= 1)
+    assert lo[-1] == pytest.approx(1.0 + 0.7 * 0.4, abs=1e-15)
+    _, g = oracle.grad(cnf, X)
+    # the empty clause contributes no gradient
+    assert g[-1, 0] == pytest.approx(-0.4, abs=1e-15)
+    assert g[-1, 1] == pytest.approx(-0.7, abs=1e-15)
+
+
+# --- the paper's worked examples ----------------------------------------------
+
+def test_golden_soft_overestimate(golden):
+    d = golden("soft_overestimate.txt")
+    cnf = _cnf(d["clauses"], 2)
+    x = np.array([d["x"]])
+    assert 1.0 - oracle.loss(cnf, x)[0, 0] == pytest.approx(d["expect_C"][0], abs=1e-15)
+    assert oracle.loss(cnf, x)[0, 0] == pytest.approx(d["expect_loss"][0], abs=1e-15)
+
+
+def test_golden_intro_example(golden):
+    d = golden("intro_example.txt")
+    cnf = _cnf(d["clauses"], 3)
+    x = np.array([d["x"]])
+    assert oracle.loss(cnf, x)[0, 0] == d["expect_loss"][0]
+    assert oracle.unsat(cnf, x)[0, 0] == d["expect_unsat"][0]
+
+
+@pytest.mark.parametrize("key", ["clauses", "alt_clauses"])
+@pytest.mark.parametrize("z1", [0.0, 1.0])
+def test_golden_appendix_normalization(golden, key, z1):
+    d = golden("appendix_normalization.txt")
+    y = np.array(d["y"])
+    # rounding of the probability of the value 1 (argmax over (1 - y, y))
+    xhat = (y > 0.5).astype(float)
+    assert xhat.tolist() == d["expect_xhat"]
+    x = np.array([list(xhat) + [z1]])
+    clauses = d[key]
+    C = [1.0 - oracle.clause_U(_cnf([c], 5).clause_lits, x[0]) for c in clauses]
+    assert C == d["expect_C"]
+    cnf = _cnf(clauses, 5)
+    L_paper = -(len(clauses) - oracle.loss(cnf, x)[0, 0])
+    assert L_paper == d["expect_L"][0]
+    assert oracle.unsat(cnf, x)[0, 0] == 1
+
+
+def test_appendix_expansions():
+    """The appendix's expanded polynomials C1, C2, C3 and the three-term
+    inclusion-exclusion rule equal 1 - prod(1 - s_i) at arbitrary points."""
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        x1, x2, x3, x4, z1 = rng.random(5)
+        xr = np.array([x1, x2, x3, x4, z1])
+        C1 = (x1 + (1 - x2) + z1 - x1 * (1 - x2) - (1 - x2) * z1 - z1 * x1 + x1 * (1 - x2) * z1)
+        C2 = ((1 - z1) + (1 - x3) + x4 - (1 - z1) * (1 - x3) - (1 - x3) * x4 - x4 * (1 - z1)
+              + (1 - z1) * (1 - x3) * x4)
+        C3 = ((1 - x1) + x3 + x3 - (1 - x1) * x3 - (1 - x1) * x3 - x3 * x3 + (1 - x1) * x3 * x3)
+        for clause, want in (([1, -2, 5], C1), ([-5, -3, 4], C2), ([-1, 3, 3], C3)):
+            codes = _cnf([clause], 5).clause_lits
+            assert 1.0 - oracle.clause_U(codes, xr) == pytest.approx(want, abs=1e-14)
+        a, b, c = rng.random(3)
+        incl_excl = a + b + c - a * b - b * c - c * a + a * b * c
+        assert 1.0 - oracle.clause_U([0, 2, 4], np.array([a, b, c])) == pytest.approx(incl_excl, abs=1e-14)
+
+
+# --- relaxed values: the multilinear expectation ------------------------------
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_loss_is_expected_unsat_count(seed):
+    """With distinct variables per clause, loss'(x) = E_{X ~ Bernoulli(x)}[#unsat(X)]."""
+    rng = np.random.default_rng(seed)
+    n = 9
+    clauses = _random_clauses(rng, n, 30, 1, 5)
+    cnf = _cnf(clauses, n)
+    x = rng.random((3, n))
+    lo = oracle.loss(cnf, x)[0]
+    for r in range(3):
+        e = 0.0
+        for bits in itertools.product([0, 1], repeat=n):
+            p = 1.0
+            for v, bv in enumerate(bits):
+                p *= x[r, v] if bv else 1.0 - x[r, v]
+            e += p * _bool_unsat(clauses, bits)
+        assert lo[r] == pytest.approx(e, rel=1e-12, abs=1e-14)
+
+
+# --- gradient ------------------------------------------------------------------
+
+def _expected_unsat(clauses, xr):
+    n = len(xr)
+    e = 0.0
+    for bits in itertools.product([0, 1], repeat=n):
+        p = 1.0
+        for v, bv in enumerate(bits):
+            p *= xr[v] if bv else 1.0 - xr[v]
+        e += p * _bool_unsat(clauses, bits)
+    return e
+
+
+def test_gradient_flip_identity():
+    """loss' is affine in each x_v (distinct variables per clause), so
+    d loss'/d x_v = loss'(x | x_v = 1) - loss'(x | x_v = 0); the right side is
+    computed by exact enumeration in Python."""
+    rng = np.random.default_rng(11)
+    n = 8
+    clauses = _random_clauses(rng, n, 25, 1, 5)
+    cnf = _cnf(clauses, n)
+    x = rng.random((2, n))
+    _, g = oracle.grad(cnf, x)
+    for r in range(2):
+        for v in range(n):
+            hi, lo = x[r].copy(), x[r].copy()
+            hi[v], lo[v] = 1.0, 0.0
+            want = _expected_unsat(clauses, hi) - _expected_unsat(clauses, lo)
+            assert g[r, v] == pytest.approx(want, rel=1e-10, abs=1e-12)
+
+
+def test_gradient_at_01_points_is_break_minus_make():
+    """At a 0/1 point the gradient is an integer: (#clauses that become
+    unsatisfied when x_v moves to 1) - (... when it moves to 0)."""
+    rng = np.random.default_rng(12)
+    n = 10
+    clauses = _random_clauses(rng, n, 60, 1, 4)
+    cnf = _cnf(clauses, n)
+    X = rng.integers(0, 2, size=(6, n)).astype(float)
+    _, g = oracle.grad(cnf, X)
+    for r in range(6):
+        for v in range(n):
+            hi, lo = X[r].astype(int).copy(), X[r].astype(int).copy()
+            hi[v], lo[v] = 1, 0
+            assert g[r, v] == float(_bool_unsat(clauses, hi) - _bool_unsat(clauses, lo))
+
+
+def _torch_loss(clauses, x):
+    """Eq. (2) and Eq. (5) in torch ops, for autograd."""
+    total = x.new_zeros(x.shape[0])
+    for c in clauses:
+        u = x.new_ones(x.shape[0])
+        for l in c:
+            xv = x[:, abs(l) - 1]
+            s = xv if l > 0 else 1.0 - xv
+            u = u * (1.0 - s)
+        total = total + u
+    return total
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_gradient_matches_autograd_with_repeats(seed):
+    rng = np.random.default_rng(seed)
+    n = 12
+    clauses = _random_clauses(rng, n, 50, 0, 7, distinct=False, allow_empty=True)
+    clauses += [[2, 2, -7], [3, -3], [5, 5, 5, 5]]
+    cnf = _cnf(clauses, n)
+    x = rng.random((4, n))
+    lo, g = oracle.grad(cnf, x)
+    xt = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    L = _torch_loss(clauses, xt)
+    L.sum().backward()
+    np.testing.assert_allclose(lo[0], L.detach().numpy(), rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(g, xt.grad.numpy(), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(oracle.grad_def(cnf, x), xt.grad.numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_central_fd_exact_for_low_degree():
+    """Each clause is a polynomial of degree <= 2 in any variable when that
+    variable appears at most twice, so the central difference is exact up
+    to rounding."""
+    rng = np.random.default_rng(21)
+    n = 15
+    clauses = _random_clauses(rng, n, 70, 1, 6)
+    clauses += [[4, 4, 9], [-6, -6]]
+    cnf = _cnf(clauses, n)
+    x = rng.random((3, n))
+    _, g = oracle.grad(cnf, x)
+    vs = np.arange(n)
+    fd = oracle.fd_grad(cnf, x, vs, 1e-3)
+    np.testing.assert_allclose(fd, g, rtol=1e-9, atol=1e-11)
+
+
+def test_zero_safe_partials():
+    """Clauses with 0, 1, 2 and all factors exactly zero: the product over the
+    other literals is nonzero only when all other factors are nonzero."""
+    # x = (1, 1, 1, 0, 0.3): a positive literal of x1..x3 has factor 0,
+    # NOT x4 has factor 0, x4 has factor 1, x5 has 0.7 and NOT x5 has 0.3.
+    x = np.array([[1.0, 1.0, 1.0, 0.0, 0.3]])
+    clauses = [[5, 4, 3],       # one zero factor (x3): only x3 gets -0.7
+               [1, 2, 5],       # two zero factors: no gradient at all
+               [1, 2, 3],       # all factors zero: no gradient
+               [-1, -2, 5]]     # no zero factor: +0.7, +0.7, -1
+    cnf = _cnf(clauses, 5)
+    lo, g = oracle.grad(cnf, x)
+    np.testing.assert_allclose(g[0], [0.7, 0.7, -0.7, 0.0, -1.0], rtol=0, atol=1e-15)
+    assert lo[0, 0] == pytest.approx(0.7, abs=1e-15)
+    np.testing.assert_allclose(oracle.grad_def(cnf, x), g, rtol=0, atol=1e-15)
+
+
+def test_grad_modes_agree_on_generated_instances():
+    cnf = I.structured_mixed(n=20_000, m=40_000, n_comm=20, seed=99)
+    rng = np.random.default_rng(0)
+    x = rng.random((2, cnf.n))
+    lo, g = oracle.grad(cnf, x)
+    np.testing.assert_allclose(oracle.grad_def(cnf, x), g, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(oracle.loss(cnf, x), lo, rtol=1e-14)
+
+
+# --- update rules against torch.optim -----------------------------------------
+
+def test_sgd_step_matches_torch_optim():
+    rng = np.random.default_rng(31)
+    x = rng.random((3, 40))
+    g = rng.normal(size=(3, 40)) * 5
+    p = torch.nn.Parameter(torch.tensor(x))
+    opt = torch.optim.SGD([p], lr=0.1)
+    p.grad = torch.tensor(g)
+    opt.step()
+    with torch.no_grad():
+        p.clamp_(0.0, 1.0)
+    np.testing.assert_allclose(oracle.step_sgd(x, g, 0.1), p.detach().numpy(), rtol=0, atol=1e-15)
+
+
+def test_adam_steps_match_torch_optim():
+    rng = np.random.default_rng(32)
+    x = rng.random((2, 30))
+    p = torch.nn.Parameter(torch.tensor(x))
+    opt = torch.optim.Adam([p], lr=0.5, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros_like(x)
+    v = np.zeros_like(x)
+    for t in range(1, 6):
+        g = rng.normal(size=x.shape)
+        p.grad = torch.tensor(g)
+        opt.step()
+        with torch.no_grad():
+            p.clamp_(0.0, 1.0)
+        x, m, v = oracle.step_adam(x, m, v, g, t, lr=0.5)
+        np.testing.assert_allclose(x, p.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+# --- rounding, counting and selection ------------------------------------------
+
+def test_unsat_count_with_ties_at_half():
+    rng = np.random.default_rng(41)
+    n = 30
+    clauses = _random_clauses(rng, n, 200, 1, 5)
+    cnf = _cnf(clauses, n)
+    x = rng.random((5, n))
+    x[:, ::4] = 0.5          # exact ties round to 0
+    got = oracle.unsat(cnf, x)[0]
+    for r in range(5):
+        assign = [1 if xv > 0.5 else 0 for xv in x[r]]
+        assert got[r] == _bool_unsat(clauses, assign)
+
+
+def test_planted_assignment_satisfies_everything():
+    cnf = I.planted_ksat(500, 2130, 3, seed=5)
+    x = cnf.planted[None, :].astype(float)
+    assert oracle.unsat(cnf, x)[0, 0] == 0
+    assert oracle.loss(cnf, x)[0, 0] == 0.0
+
+
+def test_best_is_first_minimum():
+    rng = np.random.default_rng(51)
+    u = rng.integers(0, 4, size=(20, 16)).astype(np.int32)
+    np.testing.assert_array_equal(oracle.best(u), np.argmin(u, axis=1))
+
+
+# --- batches and restarts --------------------------------------------------------
+
+def test_batch_equals_formulas_alone():
+    fs = [I.planted_ksat(30 + 7 * i, 120 + 20 * i, 3, seed=100 + i) for i in range(4)]
+    batch = I.concat(fs)
+    rng = np.random.default_rng(61)
+    x = rng.random((3, batch.n))
+    lo, g = oracle.grad(batch, x)
+    us = oracle.unsat(batch, x)
+    for f, sub in enumerate(fs):
+        v0, v1 = batch.formula_var_begin[f], batch.formula_var_begin[f + 1]
+        lo_f, g_f = oracle.grad(sub, x[:, v0:v1])
+        np.testing.assert_array_equal(lo[f], lo_f[0])
+        np.testing.assert_array_equal(g[:, v0:v1], g_f)
+        np.testing.assert_array_equal(us[f], oracle.unsat(sub, x[:, v0:v1])[0])
+
+
+def test_restart_permutation_equivariance():
+    cnf = I.planted_ksat(100, 426, 3, seed=7)
+    rng = np.random.default_rng(62)
+    x = rng.random((8, cnf.n))
+    perm = rng.permutation(8)
+    lo, g = oracle.grad(cnf, x)
+    lo_p, g_p = oracle.grad(cnf, x[perm])
+    np.testing.assert_array_equal(lo_p[0], lo[0][perm])
+    np.testing.assert_array_equal(g_p, g[perm])
+
+
+# --- the counter-based initial state ------------------------------------------
+
+def test_splitmix64_reference_outputs():
+    """Published reference outputs of SplitMix64 seeded with 1234567."""
+    got = oracle.splitmix64(1234567, 5).tolist()
+    assert got == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                   4593380528125082431, 16408922859458223821]
+
+
+def test_init_state_is_uniform_on_a_24bit_grid():
+    x = oracle.init_state(0x6A150001, 500, 64)
+    assert x.min() >= 0.0 and x.max() < 1.0
+    assert np.all(x * 2 ** 24 == np.floor(x * 2 ** 24))
+    assert abs(x.mean() - 0.5) < 0.01
+    assert abs(x.var() - 1.0 / 12.0) < 0.005
+    assert len(np.unique(x)) > 0.99 * x.size
+    # different seeds give different states
+    assert not np.array_equal(x, oracle.init_state(0x6A150002, 500, 64))
