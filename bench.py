@@ -1,0 +1,210 @@
+#!/usr/bin/env python
+"""Throughput of the fused relaxed-CNF descent step on one MI355X.
+
+A timed step is one pass of the whole hot path over the restart batch:
+clause products and loss, the gathered gradient with the fused projected
+update, and the exact unsat count of round(x) for every restart (all inside
+galsat_step, with per-step loss and unsat traces); the K timed steps end
+with the hand-off (galsat_round_check: ballot/popcount count, best restart
+per formula and its assignment).  The state lives in HBM before the timed
+region starts.
+
+Prints ONE JSON line.  `value` = literal-evaluations per second
+(R * L * K / time), `roofline` = the dominant kernel's algorithmic bytes per
+launch over its event-timed average duration against the 8 TB/s HBM peak,
+`cpu_baseline` = the FP64 oracle on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "fwd+bwd literal-evals/s & % HBM peak; batched vs plain, 1e-5 rel vs FP64"
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_28796_amd", "csrc", "galsat_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic(workload: str, kernel: str):
+    """Measured HBM bytes per launch from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*(\w+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def algorithmic_bytes(cnf, R, info, optimizer):
+    """Compulsory bytes the variable pass must move per launch: the
+    variable-major CSR, the clause-major CSR of the clauses it recomputes,
+    the stored partial rows it reads, x read once and the next x written
+    once (+ Adam moments read and written)."""
+    n, m, L = cnf.n, cnf.m, cnf.L
+    stored = int(info["stored_lits"])
+    krec = int(info["recompute_max_len"])
+    import numpy as np
+    lens = np.diff(cnf.clause_ptr)
+    rec = lens <= krec
+    m_rec, L_rec = int(rec.sum()), int(lens[rec].sum())
+    b = 4 * (n + 1) + 4 * L + 4 * (m_rec + 1) + 4 * L_rec + 8 * n * R + 4 * R * stored
+    if optimizer == "adam":
+        b += 16 * n * R
+    return b
+
+
+def cpu_baseline(cnf, R, lr, budget_s: float):
+    """The FP64 oracle's full step (gradient, unsat count, update) on the same
+    instance, all restarts, repeated until about budget_s seconds."""
+    import numpy as np
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    x = np.random.default_rng(0).random((R, cnf.n))
+    steps, t = 0, 0.0
+    while t < budget_s and steps < 20:
+        t0 = time.perf_counter()
+        _, _, _, x = oracle.full_step(cnf, x, lr)
+        t += time.perf_counter() - t0
+        steps += 1
+    v = R * cnf.L * steps / t
+    return {"value": v, "unit": "literal-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full FP64 steps (all {R} restarts) of the same instance, "
+                      f"{t:.1f} s", "seconds": round(t, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="planted3sat_n1e5")
+    ap.add_argument("--partials", default=None, help="auto | store | recompute")
+    ap.add_argument("--plan", default=None, help="plan override, e.g. lpi=64,rpl=4")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel run")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(restart or formula sharding across GPUs is a design note, not implemented).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2603_28796_amd import inputs as I
+    from paper_2603_28796_amd.galsat import Problem
+
+    w = I.WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    cnf = w.make()
+    log(f"[bench] workload {w.key}: n={cnf.n} m={cnf.m} L={cnf.L} F={cnf.F} R={w.restarts} "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    R = w.restarts
+    partials = args.partials or {0: "auto", 1: "store", 2: "recompute"}[w.recompute]
+    torch.cuda.set_device(0)
+    prob = Problem(cnf, R, lr=w.lr, partials=partials, plan_override=args.plan)
+    info = prob.info()
+    log(f"[bench] plan: {info}")
+    x = prob.init_state(I.SEED_BASE + 2)
+    K, W = args.steps, args.warmup
+    FR = cnf.F * R
+    lt = torch.empty((max(K, W), cnf.F, R), dtype=torch.float32, device="cuda")
+    ut = torch.empty((max(K, W), cnf.F, R), dtype=torch.int32, device="cuda")
+
+    if W > 0:
+        prob.step(x, W, loss_trace=lt[:W], unsat_trace=ut[:W], trace=True)
+        prob.round_check(x)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {W} steps done")
+
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    prob.step(x, K, loss_trace=lt[:K], unsat_trace=ut[:K], trace=True)
+    unsat, best, assign = prob.round_check(x)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    value = R * cnf.L * K / (ms / 1e3)
+    log(f"[bench] timed {K} steps: {ms:.2f} ms ({ms / K:.4f} ms/step), {value:.4e} lit-evals/s; "
+        f"min unsat {int(unsat.min())}, final mean loss {float(lt[K - 1].mean()):.3f}")
+
+    roofline = None
+    kernels = None
+    if not args.no_profile:
+        prob.profile(True)
+        prob.step(x, K, loss_trace=lt[:K], unsat_trace=ut[:K], trace=True)
+        prob.round_check(x)
+        torch.cuda.synchronize()
+        kernels = prob.kernel_times()
+        prob.profile(False)
+        log(f"[bench] kernel times: {kernels}")
+        launches, tot = kernels.get("var_pass", (0, 0.0))
+        if launches:
+            avg_ms = tot / launches
+            ab = algorithmic_bytes(cnf, R, info, "sgd")
+            achieved = ab / (avg_ms / 1e3) / 1e9
+            traffic = read_traffic(w.key, "var_pass")
+            roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": traffic, "kernel": "k_var_pass",
+                        "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_ms, 5)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline (oracle, ~{args.cpu_seconds:.0f} s)")
+        cpu = cpu_baseline(cnf, R, w.lr, args.cpu_seconds)
+        log(f"[bench] cpu baseline: {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "literal-evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.key, "description": w.description, "n": cnf.n, "m": cnf.m,
+                   "L": cnf.L, "formulas": cnf.F, "restarts": R, "lr": w.lr, "partials": partials,
+                   "lanes_per_item": info["lanes_per_item"],
+                   "restarts_per_lane": info["restarts_per_lane"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_ms": {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 5)}
+                      for k, v in (kernels or {}).items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

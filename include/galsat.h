@@ -1,0 +1,256 @@
+/*
+ * galsat.h -- C ABI of libgalsat: gradient descent on the relaxed algebraic
+ * encoding of CNF formulas, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (GaloisSAT, Section 3.2 "Differentiable SAT Formulation"):
+ *   Eq. (1) NOT x = 1 - x, x AND y = x*y, x OR y = x + y - x*y;
+ *   Eq. (2) a clause of literals with truth values s_i evaluates to
+ *           C = 1 - prod_i (1 - s_i), exactly its satisfaction at 0/1 points;
+ *   Eq. (5) the loss is L = -sum_t C_t.
+ * The library evaluates, for a batch of R relaxed assignments ("restarts",
+ * the paper's batch dimension B of independent random initialisations)
+ * per formula:
+ *   loss'[f][r] = sum_{t in f} U_t,  U_t = prod_i (1 - s_i) = 1 - C_t,
+ * which is m_f + L (zero exactly on satisfying 0/1 points; same gradient),
+ * its gradient with respect to every x[v][r], a fused projected-gradient
+ * (or Adam, as in the paper's appendix "Experiment Setup") update, and the
+ * exact number of unsatisfied clauses of the rounded assignment
+ * x_hat = [x > 0.5] (a tie at 0.5 rounds to 0, the first maximal index of
+ * the argmax of Eq. (4) over the pair (1 - x, x)).
+ *
+ * Conventions shared by every call
+ *   - Literal code: code = 2*v + neg (neg = 1 for a negated literal), v a
+ *     0-based global variable id.  A negated literal's clause factor is
+ *     x_v, a positive literal's is 1 - x_v.
+ *   - State x: FP32, variable-major [n][ldx] with the R restarts of a
+ *     variable contiguous; ldx >= R.  Values outside [0,1] are accepted by
+ *     galsat_loss_grad; galsat_step keeps x inside [0,1].
+ *   - Per-(formula, restart) outputs are laid out [F][R] (index f*R + r).
+ *   - Every pointer to state, gradient and output arrays is a DEVICE pointer
+ *     owned by the caller (for example a torch tensor's data_ptr()); the
+ *     library never frees it.
+ *   - Calls are asynchronous and ordered on the HIP stream passed in
+ *     (hipStream_t as void*; NULL = the default stream).  Outputs are valid
+ *     once that stream has been synchronised.
+ *   - Results are deterministic: for a given handle and inputs every output
+ *     is bitwise reproducible (no floating-point atomics anywhere).
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Errors: every call returns galsat_status.  Argument and CSR
+ *     validation errors are reported synchronously and leave the handle
+ *     usable.  A device error (a failed launch or allocation) is sticky: the
+ *     handle then fails every later call with GALSAT_EDEVICE.
+ *     galsat_last_error() gives a message for the most recent failure.
+ */
+#ifndef GALSAT_H
+#define GALSAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GALSAT_OK = 0,
+  GALSAT_EINVAL = -1,       /* bad argument or malformed CSR */
+  GALSAT_ENOMEM = -2,       /* device allocation failed or workspace budget too small */
+  GALSAT_EDEVICE = -3,      /* HIP runtime error (sticky on the handle) */
+  GALSAT_EOVERFLOW = -4,    /* a size does not fit the int32 CSR or the index range */
+  GALSAT_EUNSUPPORTED = -5  /* valid request the library does not implement */
+} galsat_status;
+
+typedef struct galsat_ctx* galsat_handle;
+
+/* A batch of F independent CNF formulas in both CSR orientations.
+ * Formula f owns the contiguous variable ids [formula_var_begin[f],
+ * formula_var_begin[f+1]) and clauses [formula_clause_begin[f],
+ * formula_clause_begin[f+1]); every literal of a clause must name a
+ * variable of the clause's formula.
+ *
+ *   clause_ptr [m+1]  clause-major offsets: clause t owns literal positions
+ *                     [clause_ptr[t], clause_ptr[t+1]) of clause_lits;
+ *                     clause_ptr[0] = 0, non-decreasing, clause_ptr[m] = L.
+ *                     Empty clauses (U = 1, always unsatisfied, no
+ *                     gradient), repeated variables and complementary
+ *                     literals inside one clause are all accepted.
+ *   clause_lits [L]   literal codes.
+ *   var_ptr [n+1]     variable-major offsets into var_occ.
+ *   var_occ [L]       for variable v, the positions p of clause_lits with
+ *                     clause_lits[p] >> 1 == v: exactly the transpose of the
+ *                     clause-major CSR, every position exactly once.  The
+ *                     order inside a variable is the order in which its
+ *                     gradient contributions are summed.
+ * All arrays are int32; L < 2^31.  With inputs_on_device = 0 they are host
+ * pointers, with 1 device pointers.  galsat_create copies them: the caller
+ * may free or reuse them as soon as it returns.
+ */
+typedef struct {
+  int32_t num_formulas;                 /* F >= 1 */
+  const int32_t* formula_var_begin;     /* [F+1]; may be NULL when F == 1 */
+  const int32_t* formula_clause_begin;  /* [F+1]; may be NULL when F == 1 */
+  int32_t n_vars;                       /* n >= 0 (total over formulas) */
+  int32_t n_clauses;                    /* m >= 0 */
+  int32_t n_lits;                       /* L >= 0 */
+  const int32_t* clause_ptr;
+  const int32_t* clause_lits;
+  const int32_t* var_ptr;
+  const int32_t* var_occ;
+  int32_t restarts;                     /* R >= 1, the same for every formula */
+  int32_t inputs_on_device;
+} galsat_problem;
+
+enum { GALSAT_OPT_SGD_CLAMP = 0, GALSAT_OPT_ADAM = 1 };
+
+/* How the backward obtains each literal's partial derivative
+ * prod_{i != j} (1 - s_i):
+ *   STORE      a clause-parallel pass forms them from prefix and suffix
+ *              products and stores them; a variable-parallel pass sums
+ *              them in var_occ order.
+ *   RECOMPUTE  the variable-parallel pass recomputes them from x, so no
+ *              per-literal or per-clause values are kept between passes.
+ *   AUTO       clauses up to recompute_max_len literals recompute, longer
+ *              ones store, within workspace_budget_bytes. */
+enum { GALSAT_PARTIALS_AUTO = 0, GALSAT_PARTIALS_STORE = 1, GALSAT_PARTIALS_RECOMPUTE = 2 };
+
+/* Execution schedule of galsat_step:
+ *   GENERAL  multi-kernel passes per step over all formulas at once;
+ *   BATCHED  one persistent launch runs every step for every
+ *            (formula, restart group) work item with that item's state in
+ *            LDS (formulas too large for LDS fall back to GENERAL);
+ *   PLAIN    one formula at a time, kernels launched per pass per step
+ *            (the reference point for batching, not a fast path);
+ *   AUTO     BATCHED when every formula fits LDS, else GENERAL. */
+enum { GALSAT_SCHED_AUTO = 0, GALSAT_SCHED_GENERAL = 1, GALSAT_SCHED_BATCHED = 2,
+       GALSAT_SCHED_PLAIN = 3 };
+
+typedef struct {
+  int32_t optimizer;         /* GALSAT_OPT_*; default SGD_CLAMP */
+  float lr;                  /* default 0.1 */
+  float beta1, beta2, eps;   /* Adam only; defaults 0.9, 0.999, 1e-8 */
+  int32_t partials;          /* GALSAT_PARTIALS_*; default AUTO */
+  int32_t recompute_max_len; /* AUTO threshold in literals; 0 = library default */
+  size_t workspace_budget_bytes; /* cap on stored partials; 0 = no cap */
+  int32_t validate;          /* 1 (default): also check that var_occ is a permutation */
+  int32_t schedule;          /* GALSAT_SCHED_*; default AUTO */
+  int32_t use_graph;         /* 1: galsat_step replays a captured hipGraph (GENERAL) */
+  const char* plan_override; /* NULL, or "lpi=L,rpl=P,krec=K": lanes per item
+                              (4..64), restarts per lane (1, 2, 4), recompute threshold */
+} galsat_options;
+
+/* Fills *opt with the defaults listed above. */
+void galsat_default_options(galsat_options* opt);
+
+/* Validates and copies the problem to the device, derives the occurrence
+ * tables the kernels use, chooses a plan and allocates its workspace.
+ * stream: used for the uploads (synchronised before returning).
+ * On success *out holds a new handle; on failure *out is NULL and the
+ * message is available from galsat_last_error(NULL). */
+galsat_status galsat_create(const galsat_problem* prob, const galsat_options* opt, void* stream,
+                            galsat_handle* out);
+
+/* Frees all device memory, graphs and the handle.  NULL is accepted. */
+galsat_status galsat_destroy(galsat_handle h);
+
+/* Relaxed initial state (the paper initialises each batch element
+ * independently at random, Section 3.2): x[v][r] = (hash >> 40) * 2^-24 with
+ * hash = SplitMix64mix(seed XOR SplitMix64mix(v * 2^32 + r + 0x9e3779b97f4a7c15)),
+ * uniform on a 2^-24 grid in [0, 1).  Writes x[n][ldx] for r < R. */
+galsat_status galsat_init_state(galsat_handle h, float* x, int32_t ldx, uint64_t seed,
+                                void* stream);
+
+/* Forward and (optionally) backward at x (Eq. 2 and Eq. 5).
+ *   x        device FP32 [n][ldx], read only.
+ *   loss     device FP32 [F*R]: loss'[f][r] (required).
+ *   grad     device FP32 [n][ldx] or NULL (loss only).  When given:
+ *            grad[v][r] = w[f(v)][r] * d loss'[f(v)][r] / d x[v][r] with
+ *            w = upstream, or 1 when upstream is NULL (autograd backward).
+ *   upstream device FP32 [F*R] or NULL.
+ * Entries grad[v][r] for r >= R are not written. */
+galsat_status galsat_loss_grad(galsat_handle h, const float* x, int32_t ldx, const float* upstream,
+                               float* loss, float* grad, void* stream);
+
+/* `steps` iterations, each evaluated at the current x_k with every variable
+ * updated from the same gradient (Jacobi):
+ *   SGD_CLAMP  x_{k+1} = min(1, max(0, x_k - lr * g_k))
+ *   ADAM       m, v moments and bias correction at the handle's step
+ *              counter t (starting at 1, advanced once per step), then the
+ *              same clamp.  opt_state: device FP32 [2][n][ldx] (m then v),
+ *              zero before the first step; NULL for SGD.
+ * x is updated in place.  loss_trace ([steps][F*R] FP32) and unsat_trace
+ * ([steps][F*R] int32), each optional, receive loss'(x_k) and the exact
+ * unsatisfied-clause count of round(x_k) for every step k. */
+galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, float* opt_state, int32_t steps,
+                          float* loss_trace, int32_t* unsat_trace, void* stream);
+
+/* Rounds x (x > 0.5 -> 1; an x that is already 0/1 is used as given),
+ * counts unsatisfied clauses exactly per (formula, restart) with wavefront
+ * ballot and popcount, and picks per formula the restart with the fewest
+ * (ties to the lowest restart index): the hand-off of the GPU stage.
+ *   unsat        device int32 [F*R]
+ *   best_restart device int32 [F] or NULL
+ *   best_assign  device uint8 [n] or NULL: the rounded assignment of each
+ *                variable in its formula's best restart. */
+galsat_status galsat_round_check(galsat_handle h, const float* x, int32_t ldx, int32_t* unsat,
+                                 int32_t* best_restart, uint8_t* best_assign, void* stream);
+
+/* Sets the Adam step counter (the next step uses t + 1); 0 restarts the bias
+ * correction.  For checkpoint and resume. */
+galsat_status galsat_set_adam_step(galsat_handle h, int32_t t);
+
+/* Plan and size information (host values). */
+typedef struct {
+  int32_t num_formulas, n_vars, n_clauses, n_lits, restarts;
+  int32_t max_clause_len;
+  int32_t recompute_max_len;    /* clauses up to this length recompute partials */
+  int64_t stored_lits;          /* literal occurrences whose partials are stored */
+  int32_t schedule;             /* schedule galsat_step uses (GALSAT_SCHED_*) */
+  int32_t lanes_per_item;       /* restarts lanes of one variable or clause */
+  int32_t restarts_per_lane;
+  int32_t var_chunks, clause_chunks;
+  int32_t batched_items;        /* work items of the BATCHED schedule */
+  size_t device_bytes;          /* device memory held by the handle */
+  int32_t adam_step;
+} galsat_info;
+
+galsat_status galsat_get_info(galsat_handle h, galsat_info* info);
+
+/* Per-kernel timing.  While profiling is enabled on a handle, every kernel
+ * launch of the handle is bracketed by a pair of HIP events recorded on the
+ * stream of the call, so each duration is that kernel's own time on its
+ * stream.  galsat_profile(h, 1) clears the record and starts it;
+ * galsat_profile(h, 0) stops it.  galsat_kernel_times synchronises the
+ * recorded events and returns, per kernel kind, the number of launches and
+ * their summed duration in milliseconds. */
+enum {
+  GALSAT_K_VAR_PASS = 0,     /* variable-parallel gather + fused update / gradient */
+  GALSAT_K_CLAUSE_PASS = 1,  /* clause-parallel forward and stored partials */
+  GALSAT_K_FINALIZE = 2,     /* fixed-order reduction of per-chunk partial sums */
+  GALSAT_K_COPY = 3,         /* state copy between the caller's and internal layouts */
+  GALSAT_K_PACK = 4,         /* rounding bit-pack (ballot) */
+  GALSAT_K_COUNT = 5,        /* unsat count (ballot + popcount) */
+  GALSAT_K_SELECT = 6,       /* best restart and its assignment */
+  GALSAT_K_BATCHED = 7,      /* persistent batched step loop */
+  GALSAT_K_KINDS = 8
+};
+
+typedef struct {
+  int32_t launches[GALSAT_K_KINDS];
+  double total_ms[GALSAT_K_KINDS];
+} galsat_kernel_stats;
+
+galsat_status galsat_profile(galsat_handle h, int32_t enable);
+galsat_status galsat_kernel_times(galsat_handle h, galsat_kernel_stats* out);
+
+/* Static description of a status code. */
+const char* galsat_status_string(galsat_status s);
+
+/* Message for the most recent failure on h (or of galsat_create when h is
+ * NULL); "" if none.  Valid until the next call on the same handle. */
+const char* galsat_last_error(galsat_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GALSAT_H */

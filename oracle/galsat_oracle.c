@@ -56,15 +56,6 @@ static double factor(int32_t code, const double* xr) {
 /* d(factor)/dx_v: -1 for a positive literal, +1 for a negated one. */
 static double factor_slope(int32_t code) { return (code & 1) ? 1.0 : -1.0; }
 
-static int formula_of_clause(int32_t F, const int32_t* fcb, int64_t t) {
-  int lo = 0, hi = F - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) / 2;
-    if (fcb[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 /* U_t = prod over the clause's literals of (1 - s_i)  (Eq. 2: C_t = 1 - U_t). */
 double oracle_clause_U(int32_t k, const int32_t* codes, const double* xr) {
   double u = 1.0;
@@ -167,35 +158,47 @@ void oracle_grad_def(int32_t n, int32_t F, const int32_t* fcb, const int32_t* cp
 /* Central finite difference of loss' in x[r][v] for the listed variables,
  * restricted to the clauses that contain v (all other clauses cancel
  * exactly): (sum_{t ni v} U_t(x + h e_v) - U_t(x - h e_v)) / (2h).
- * out[r*nv + i] for variable vars[i].  Scans the clause-major CSR. */
+ * out[r*nv + i] for variable vars[i].  The clauses containing each listed
+ * variable are found by one scan of the clause-major CSR. */
 void oracle_fd_grad(int32_t n, int32_t m, const int32_t* cptr, const int32_t* lits, int32_t R,
                     const double* x, int32_t nv, const int32_t* vars, double h, double* out) {
 #pragma omp parallel
   {
     double* xp = (double*)malloc(sizeof(double) * (size_t)n);
-#pragma omp for schedule(dynamic, 1) collapse(2)
-    for (int32_t r = 0; r < R; ++r) {
-      for (int32_t i = 0; i < nv; ++i) {
-        const int32_t v = vars[i];
+    int64_t cap = 64;
+    int64_t* tl = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
+#pragma omp for schedule(dynamic, 1)
+    for (int32_t i = 0; i < nv; ++i) {
+      const int32_t v = vars[i];
+      int64_t cnt = 0;
+      for (int64_t t = 0; t < m; ++t) {
+        int has = 0;
+        for (int32_t p = cptr[t]; p < cptr[t + 1]; ++p)
+          if ((lits[p] >> 1) == v) has = 1;
+        if (!has) continue;
+        if (cnt == cap) {
+          cap *= 2;
+          tl = (int64_t*)realloc(tl, sizeof(int64_t) * (size_t)cap);
+        }
+        tl[cnt++] = t;
+      }
+      for (int32_t r = 0; r < R; ++r) {
         memcpy(xp, x + (int64_t)r * n, sizeof(double) * (size_t)n);
         const double x0 = xp[v];
         double up = 0.0, dn = 0.0;
-        for (int64_t t = 0; t < m; ++t) {
+        for (int64_t c = 0; c < cnt; ++c) {
+          const int64_t t = tl[c];
           const int32_t k = cptr[t + 1] - cptr[t];
-          const int32_t* c = lits + cptr[t];
-          int has = 0;
-          for (int32_t j = 0; j < k; ++j)
-            if ((c[j] >> 1) == v) has = 1;
-          if (!has) continue;
           xp[v] = x0 + h;
-          up += oracle_clause_U(k, c, xp);
+          up += oracle_clause_U(k, lits + cptr[t], xp);
           xp[v] = x0 - h;
-          dn += oracle_clause_U(k, c, xp);
-          xp[v] = x0;
+          dn += oracle_clause_U(k, lits + cptr[t], xp);
         }
+        xp[v] = x0;
         out[(int64_t)r * nv + i] = (up - dn) / (2.0 * h);
       }
     }
+    free(tl);
     free(xp);
   }
 }

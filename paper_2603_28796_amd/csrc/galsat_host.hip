@@ -1,0 +1,882 @@
+// Host runtime of libgalsat: the C ABI declared in include/galsat.h.
+//
+// galsat_create validates the two CSR orientations, derives the
+// occurrence tables the kernels read (per var-major slot: recompute the
+// clause, or read a stored partial row), splits variables and clauses into
+// work chunks of balanced cost that never cross a formula, and sizes the
+// workspace.  The per-call entry points only enqueue kernels on the
+// caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "galsat_internal.h"
+
+using namespace galsat;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kDefaultRecomputeMaxLen = 8;
+constexpr int kTargetBlocks = 2048;  // blocks per general-pass launch (256 CUs x 8)
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+inline int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Work chunks over per-formula item ranges: consecutive items with total
+// cost <= target, never crossing a formula boundary.
+struct Chunks {
+  std::vector<int32_t> beg, end;   // item range of each chunk
+  std::vector<int32_t> f_first;    // [F+1] first chunk of each formula
+  int count() const { return (int)beg.size(); }
+};
+
+Chunks make_chunks(int F, const std::vector<int64_t>& f_item_beg, const std::vector<int64_t>& cost_prefix,
+                   int64_t target) {
+  Chunks c;
+  c.f_first.assign((size_t)F + 1, 0);
+  if (target < 1) target = 1;
+  for (int f = 0; f < F; ++f) {
+    c.f_first[f] = c.count();
+    int64_t i = f_item_beg[f];
+    const int64_t e = f_item_beg[f + 1];
+    while (i < e) {
+      int64_t j = i + 1;
+      // extend while the chunk stays within target
+      const int64_t limit = cost_prefix[i] + target;
+      int64_t lo = j, hi = e;
+      while (lo < hi) {  // largest j in [i+1, e] with prefix[j] <= limit
+        int64_t mid = (lo + hi + 1) / 2;
+        if (cost_prefix[mid] <= limit) lo = mid; else hi = mid - 1;
+      }
+      j = std::max(lo, i + 1);
+      c.beg.push_back((int32_t)i);
+      c.end.push_back((int32_t)j);
+      i = j;
+    }
+  }
+  c.f_first[F] = c.count();
+  return c;
+}
+
+}  // namespace
+
+struct galsat_ctx {
+  int device = 0;
+  int32_t F = 1, n = 0, m = 0, L = 0, R = 1;
+  galsat_options opt{};
+  std::string err;
+  bool sticky = false;
+  int32_t kmax = 0;
+  int32_t krec = 0;
+  int64_t stored = 0;
+  int schedule = GALSAT_SCHED_GENERAL;
+  Tile tile;
+  int32_t ld = 0;    // internal state row stride (floats)
+  int64_t ldD = 0;
+  int adam_t = 0;
+  size_t device_bytes = 0;
+  std::vector<void*> allocs;
+
+  std::vector<int32_t> h_fvb, h_fcb;
+  Chunks vch, sch, ach;  // var chunks, stored-clause chunks, all-clause chunks
+
+  // device tables
+  int32_t *clause_ptr = nullptr, *clause_lits = nullptr, *var_ptr = nullptr, *var_occ = nullptr;
+  int32_t *occ_rec = nullptr, *lit_dslot = nullptr, *var_formula = nullptr, *stored_ids = nullptr;
+  int32_t *vch_beg = nullptr, *vch_end = nullptr, *sch_beg = nullptr, *sch_end = nullptr;
+  int32_t *ach_beg = nullptr, *ach_end = nullptr;
+  int32_t *fin_step_a0 = nullptr, *fin_step_a1 = nullptr, *fin_step_b0 = nullptr,
+          *fin_step_b1 = nullptr;
+  int32_t *fin_all_a0 = nullptr, *fin_all_a1 = nullptr, *fin_none = nullptr;
+  // Empty clauses have no occurrence, so the step's variable pass never
+  // sees them: the step's finalize adds n_empty.  Passes over every clause
+  // (loss only, round check) count them themselves and add zero_empty.
+  int32_t *n_empty = nullptr, *zero_empty = nullptr;
+  int32_t *f_vbeg = nullptr, *f_cbeg = nullptr;
+  // workspace
+  float *D = nullptr, *xa = nullptr, *xb = nullptr;
+  double* loss_part = nullptr;
+  int32_t* unsat_part = nullptr;
+  uint64_t* bits = nullptr;
+  int32_t* best_tmp = nullptr;
+  int32_t* unsat_tmp = nullptr;
+  int32_t* work_counter = nullptr;
+
+  // per-kernel event timing (galsat_profile)
+  bool prof = false;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+
+  hipEvent_t get_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+
+  void release_records() {
+    for (auto& r : recs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+
+  ~galsat_ctx() {
+    release_records();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+
+  galsat_status fail(galsat_status s, const std::string& msg) {
+    err = msg;
+    if (s == GALSAT_EDEVICE) sticky = true;
+    return s;
+  }
+
+  galsat_status dev_fail(hipError_t e, const char* what) {
+    return fail(GALSAT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) return e;
+    allocs.push_back(q);
+    device_bytes += count * sizeof(T);
+    *p = static_cast<T*>(q);
+    return hipSuccess;
+  }
+
+  template <typename T>
+  hipError_t upload(T** p, const T* src, size_t count, hipStream_t s) {
+    hipError_t e = alloc(p, count);
+    if (e != hipSuccess || count == 0) return e;
+    return hipMemcpyAsync(*p, src, count * sizeof(T), hipMemcpyHostToDevice, s);
+  }
+};
+
+// Brackets the launches of its scope with a pair of events when the
+// handle is profiling.
+struct ProfScope {
+  galsat_ctx* h;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(galsat_ctx* h_, int kind_, hipStream_t s_) : h(h_), kind(kind_), s(s_) {
+    if (!h->prof) return;
+    a = h->get_event();
+    b = h->get_event();
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      h->recs.push_back({kind, a, b});
+    }
+  }
+};
+
+#define GS_CHECK_HANDLE(h)                                                      \
+  do {                                                                          \
+    if (!(h)) return GALSAT_EINVAL;                                             \
+    if ((h)->sticky) return GALSAT_EDEVICE;                                     \
+  } while (0)
+
+#define GS_HIP(h, expr, what)                                                   \
+  do {                                                                          \
+    hipError_t _e = (expr);                                                     \
+    if (_e != hipSuccess) return (h)->dev_fail(_e, what);                       \
+  } while (0)
+
+extern "C" {
+
+void galsat_default_options(galsat_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->optimizer = GALSAT_OPT_SGD_CLAMP;
+  o->lr = 0.1f;
+  o->beta1 = 0.9f;
+  o->beta2 = 0.999f;
+  o->eps = 1e-8f;
+  o->partials = GALSAT_PARTIALS_AUTO;
+  o->recompute_max_len = 0;
+  o->workspace_budget_bytes = 0;
+  o->validate = 1;
+  o->schedule = GALSAT_SCHED_AUTO;
+  o->use_graph = 0;
+  o->plan_override = nullptr;
+}
+
+const char* galsat_status_string(galsat_status s) {
+  switch (s) {
+    case GALSAT_OK: return "ok";
+    case GALSAT_EINVAL: return "invalid argument";
+    case GALSAT_ENOMEM: return "out of device memory or workspace budget";
+    case GALSAT_EDEVICE: return "device error";
+    case GALSAT_EOVERFLOW: return "size overflow";
+    case GALSAT_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* galsat_last_error(galsat_handle h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"
+
+namespace {
+
+galsat_status create_fail(galsat_status s, const std::string& msg) {
+  g_create_error = msg;
+  return s;
+}
+
+// Parses "key=value,key=value" plan overrides: lpi, rpl, krec.
+void apply_override(const char* spec, int* lpi, int* rpl, int* krec) {
+  if (!spec) return;
+  std::string s(spec);
+  size_t pos = 0;
+  while (pos < s.size()) {
+    size_t comma = s.find(',', pos);
+    if (comma == std::string::npos) comma = s.size();
+    std::string kv = s.substr(pos, comma - pos);
+    size_t eq = kv.find('=');
+    if (eq != std::string::npos) {
+      std::string k = kv.substr(0, eq);
+      int v = std::atoi(kv.c_str() + eq + 1);
+      if (k == "lpi") *lpi = v;
+      else if (k == "rpl") *rpl = v;
+      else if (k == "krec") *krec = v;
+    }
+    pos = comma + 1;
+  }
+}
+
+Tile choose_tile(int R, int rpl_max) {
+  Tile t;
+  int rpl = 1;
+  if (rpl_max >= 4 && R % 4 == 0) rpl = 4;
+  else if (rpl_max >= 2 && R % 2 == 0) rpl = 2;
+  int per_lane = (R + rpl - 1) / rpl;
+  int lpi = pow2_ceil(per_lane);
+  lpi = std::max(4, std::min(64, lpi));
+  t.lpi = lpi;
+  t.rpl = rpl;
+  return t;
+}
+
+}  // namespace
+
+extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_options* opt_in,
+                                       void* stream, galsat_handle* out) {
+  g_create_error.clear();
+  if (!out) return create_fail(GALSAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!prob) return create_fail(GALSAT_EINVAL, "problem is NULL");
+  galsat_options opt;
+  if (opt_in) opt = *opt_in; else galsat_default_options(&opt);
+  const int32_t F = prob->num_formulas, n = prob->n_vars, m = prob->n_clauses, L = prob->n_lits,
+                R = prob->restarts;
+  if (F < 1) return create_fail(GALSAT_EINVAL, "num_formulas must be >= 1");
+  if (n < 0 || m < 0 || L < 0) return create_fail(GALSAT_EINVAL, "negative size");
+  if (R < 1) return create_fail(GALSAT_EINVAL, "restarts must be >= 1");
+  if (R > 65536) return create_fail(GALSAT_EOVERFLOW, "restarts above 65536");
+  if (!prob->clause_ptr || !prob->var_ptr || (L > 0 && (!prob->clause_lits || !prob->var_occ)))
+    return create_fail(GALSAT_EINVAL, "missing CSR array");
+  if (F > 1 && (!prob->formula_var_begin || !prob->formula_clause_begin))
+    return create_fail(GALSAT_EINVAL, "formula ranges are required when num_formulas > 1");
+  if (opt.optimizer != GALSAT_OPT_SGD_CLAMP && opt.optimizer != GALSAT_OPT_ADAM)
+    return create_fail(GALSAT_EINVAL, "unknown optimizer");
+  if (opt.partials < 0 || opt.partials > 2) return create_fail(GALSAT_EINVAL, "unknown partials mode");
+  if (opt.schedule < 0 || opt.schedule > 3) return create_fail(GALSAT_EINVAL, "unknown schedule");
+  if (!(opt.lr >= 0.0f) || !std::isfinite(opt.lr)) return create_fail(GALSAT_EINVAL, "lr must be finite and >= 0");
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // ---- host copies of the inputs
+  std::vector<int32_t> cp((size_t)m + 1), cl((size_t)L), vp((size_t)n + 1), vo((size_t)L);
+  std::vector<int32_t> fvb((size_t)F + 1), fcb((size_t)F + 1);
+  auto fetch = [&](std::vector<int32_t>& dst, const int32_t* src) -> hipError_t {
+    if (dst.empty()) return hipSuccess;
+    if (prob->inputs_on_device)
+      return hipMemcpy(dst.data(), src, dst.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    std::memcpy(dst.data(), src, dst.size() * sizeof(int32_t));
+    return hipSuccess;
+  };
+  hipError_t he = hipSuccess;
+  if ((he = fetch(cp, prob->clause_ptr)) != hipSuccess || (he = fetch(vp, prob->var_ptr)) != hipSuccess ||
+      (L > 0 && (he = fetch(cl, prob->clause_lits)) != hipSuccess) ||
+      (L > 0 && (he = fetch(vo, prob->var_occ)) != hipSuccess))
+    return create_fail(GALSAT_EDEVICE, std::string("copying inputs: ") + hipGetErrorString(he));
+  if (F > 1) {
+    if ((he = fetch(fvb, prob->formula_var_begin)) != hipSuccess ||
+        (he = fetch(fcb, prob->formula_clause_begin)) != hipSuccess)
+      return create_fail(GALSAT_EDEVICE, std::string("copying inputs: ") + hipGetErrorString(he));
+  } else {
+    fvb = {0, n};
+    fcb = {0, m};
+    if (prob->formula_var_begin) {
+      if ((he = fetch(fvb, prob->formula_var_begin)) != hipSuccess ||
+          (he = fetch(fcb, prob->formula_clause_begin ? prob->formula_clause_begin : nullptr)) != hipSuccess)
+        return create_fail(GALSAT_EDEVICE, "copying formula ranges");
+    }
+  }
+
+  // ---- validation
+  if (cp[0] != 0 || cp[(size_t)m] != L) return create_fail(GALSAT_EINVAL, "clause_ptr must start at 0 and end at n_lits");
+  for (int32_t t = 0; t < m; ++t)
+    if (cp[t + 1] < cp[t]) return create_fail(GALSAT_EINVAL, "clause_ptr is not non-decreasing");
+  if (vp[0] != 0 || vp[(size_t)n] != L) return create_fail(GALSAT_EINVAL, "var_ptr must start at 0 and end at n_lits");
+  for (int32_t v = 0; v < n; ++v)
+    if (vp[v + 1] < vp[v]) return create_fail(GALSAT_EINVAL, "var_ptr is not non-decreasing");
+  if (fvb[0] != 0 || fvb[F] != n || fcb[0] != 0 || fcb[F] != m)
+    return create_fail(GALSAT_EINVAL, "formula ranges must start at 0 and end at n_vars / n_clauses");
+  for (int32_t f = 0; f < F; ++f)
+    if (fvb[f + 1] < fvb[f] || fcb[f + 1] < fcb[f])
+      return create_fail(GALSAT_EINVAL, "formula ranges are not non-decreasing");
+  std::vector<int32_t> var_formula((size_t)n);
+  for (int32_t f = 0; f < F; ++f)
+    for (int32_t v = fvb[f]; v < fvb[f + 1]; ++v) var_formula[v] = f;
+  std::vector<int32_t> clause_of((size_t)L);
+  int32_t kmax = 0;
+  std::vector<int32_t> n_empty((size_t)F, 0);
+  for (int32_t f = 0; f < F; ++f) {
+    for (int32_t t = fcb[f]; t < fcb[f + 1]; ++t) {
+      const int32_t k = cp[t + 1] - cp[t];
+      kmax = std::max(kmax, k);
+      if (k == 0) n_empty[f]++;
+      for (int32_t p = cp[t]; p < cp[t + 1]; ++p) {
+        const int32_t code = cl[p];
+        if (code < 0 || (code >> 1) >= n)
+          return create_fail(GALSAT_EINVAL, "literal code out of range at position " + std::to_string(p));
+        if ((code >> 1) < fvb[f] || (code >> 1) >= fvb[f + 1])
+          return create_fail(GALSAT_EINVAL, "clause " + std::to_string(t) + " uses a variable of another formula");
+        clause_of[p] = t;
+      }
+    }
+  }
+  {
+    std::vector<uint8_t> seen(opt.validate ? (size_t)L : 0, 0);
+    for (int32_t v = 0; v < n; ++v)
+      for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
+        const int32_t p = vo[q];
+        if (p < 0 || p >= L) return create_fail(GALSAT_EINVAL, "var_occ entry out of range");
+        if ((cl[p] >> 1) != v)
+          return create_fail(GALSAT_EINVAL, "var_occ is not the transpose of clause_lits (variable " +
+                                                std::to_string(v) + ")");
+        if (opt.validate) {
+          if (seen[p]) return create_fail(GALSAT_EINVAL, "var_occ lists a position twice");
+          seen[p] = 1;
+        }
+      }
+  }
+
+  std::unique_ptr<galsat_ctx> h(new galsat_ctx());
+  h->F = F; h->n = n; h->m = m; h->L = L; h->R = R;
+  h->opt = opt;
+  h->kmax = kmax;
+  h->h_fvb = fvb;
+  h->h_fcb = fcb;
+  (void)hipGetDevice(&h->device);
+
+  // ---- plan: which clauses recompute their partials in the variable pass
+  int lpi_o = 0, rpl_o = 0, krec_o = -1;
+  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o);
+  int32_t krec;
+  if (opt.partials == GALSAT_PARTIALS_STORE) krec = -1;           // every clause stores
+  else if (opt.partials == GALSAT_PARTIALS_RECOMPUTE) krec = kmax;
+  else krec = opt.recompute_max_len > 0 ? opt.recompute_max_len : kDefaultRecomputeMaxLen;
+  if (krec_o >= -1 && opt.plan_override && std::strstr(opt.plan_override, "krec=")) krec = krec_o;
+  h->tile = choose_tile(R, 4);
+  if (lpi_o == 4 || lpi_o == 8 || lpi_o == 16 || lpi_o == 32 || lpi_o == 64) h->tile.lpi = lpi_o;
+  if ((rpl_o == 1 || rpl_o == 2 || rpl_o == 4) && R % rpl_o == 0) h->tile.rpl = rpl_o;
+  h->ld = (int32_t)round_up(R, 4);
+  h->ldD = round_up(R, 4);
+  auto count_stored = [&](int32_t kr) {
+    int64_t c = 0;
+    for (int32_t t = 0; t < m; ++t)
+      if (cp[t + 1] - cp[t] > kr && cp[t + 1] > cp[t]) c += cp[t + 1] - cp[t];
+    return c;
+  };
+  int64_t stored = count_stored(krec);
+  if (opt.workspace_budget_bytes > 0 &&
+      (size_t)stored * (size_t)h->ldD * sizeof(float) > opt.workspace_budget_bytes) {
+    if (opt.partials == GALSAT_PARTIALS_STORE)
+      return create_fail(GALSAT_ENOMEM, "stored partials exceed workspace_budget_bytes");
+    krec = kmax;  // recompute everything: no per-literal storage at all
+    stored = 0;
+  }
+  h->krec = krec;
+  h->stored = stored;
+
+  // occurrence records and stored-row numbering (var-major order)
+  std::vector<int32_t> occ_rec((size_t)L), lit_dslot(stored > 0 ? (size_t)L : 0, -1);
+  {
+    int64_t d = 0;
+    for (int32_t v = 0; v < n; ++v)
+      for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
+        const int32_t p = vo[q], t = clause_of[p];
+        if (cp[t + 1] - cp[t] > krec) {
+          occ_rec[q] = -(int32_t)(d + 1);
+          lit_dslot[p] = (int32_t)d;
+          ++d;
+        } else {
+          occ_rec[q] = t;
+        }
+      }
+  }
+  std::vector<int32_t> stored_ids;
+  std::vector<int64_t> f_sbeg((size_t)F + 1, 0);
+  for (int32_t f = 0; f < F; ++f) {
+    f_sbeg[f] = (int64_t)stored_ids.size();
+    for (int32_t t = fcb[f]; t < fcb[f + 1]; ++t)
+      if (cp[t + 1] - cp[t] > krec && cp[t + 1] > cp[t]) stored_ids.push_back(t);
+  }
+  f_sbeg[F] = (int64_t)stored_ids.size();
+
+  // ---- chunks of balanced cost
+  const int tiles = (R + h->tile.tile() - 1) / h->tile.tile();
+  const int64_t chunks_target = std::max<int64_t>(1, kTargetBlocks / std::max(1, tiles));
+  {
+    std::vector<int64_t> pre((size_t)n + 1, 0), fb(fvb.begin(), fvb.end());
+    for (int32_t v = 0; v < n; ++v) {
+      int64_t c = 1;
+      for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
+        const int32_t rec = occ_rec[q];
+        c += rec < 0 ? 1 : std::max(1, cp[rec + 1] - cp[rec] - 1);
+      }
+      pre[v + 1] = pre[v] + c;
+    }
+    h->vch = make_chunks(F, fb, pre, std::max<int64_t>(64, pre[n] / chunks_target));
+  }
+  {
+    std::vector<int64_t> pre(stored_ids.size() + 1, 0);
+    for (size_t i = 0; i < stored_ids.size(); ++i)
+      pre[i + 1] = pre[i] + 1 + 2 * (cp[stored_ids[i] + 1] - cp[stored_ids[i]]);
+    h->sch = make_chunks(F, f_sbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target));
+  }
+  {
+    std::vector<int64_t> pre((size_t)m + 1, 0), fb(fcb.begin(), fcb.end());
+    for (int32_t t = 0; t < m; ++t) pre[t + 1] = pre[t] + 1 + (cp[t + 1] - cp[t]);
+    h->ach = make_chunks(F, fb, pre, std::max<int64_t>(256, pre[m] / chunks_target));
+  }
+  const int VC = h->vch.count(), SC = h->sch.count(), AC = h->ach.count();
+  std::vector<int32_t> fsa0(F), fsa1(F), fsb0(F), fsb1(F), faa0(F), faa1(F), fnone(F, 0);
+  for (int32_t f = 0; f < F; ++f) {
+    fsa0[f] = h->vch.f_first[f];
+    fsa1[f] = h->vch.f_first[f + 1];
+    fsb0[f] = VC + h->sch.f_first[f];
+    fsb1[f] = VC + h->sch.f_first[f + 1];
+    faa0[f] = h->ach.f_first[f];
+    faa1[f] = h->ach.f_first[f + 1];
+  }
+  // schedule
+  h->schedule = opt.schedule == GALSAT_SCHED_PLAIN ? GALSAT_SCHED_PLAIN : GALSAT_SCHED_GENERAL;
+
+  // ---- device upload and workspace
+  galsat_ctx* c = h.get();
+#define UP(dst, vec)                                                                     \
+  do {                                                                                   \
+    if ((he = c->upload(&c->dst, (vec).data(), (vec).size(), s)) != hipSuccess)         \
+      return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,    \
+                         std::string("upload " #dst ": ") + hipGetErrorString(he));      \
+  } while (0)
+#define AL(dst, count)                                                                   \
+  do {                                                                                   \
+    if ((he = c->alloc(&c->dst, (size_t)(count))) != hipSuccess)                        \
+      return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,    \
+                         std::string("allocate " #dst ": ") + hipGetErrorString(he));    \
+  } while (0)
+  UP(clause_ptr, cp);
+  UP(clause_lits, cl);
+  UP(var_ptr, vp);
+  UP(var_occ, vo);
+  UP(occ_rec, occ_rec);
+  if (stored > 0) UP(lit_dslot, lit_dslot);
+  UP(var_formula, var_formula);
+  UP(stored_ids, stored_ids);
+  UP(vch_beg, c->vch.beg);
+  UP(vch_end, c->vch.end);
+  UP(sch_beg, c->sch.beg);
+  UP(sch_end, c->sch.end);
+  UP(ach_beg, c->ach.beg);
+  UP(ach_end, c->ach.end);
+  UP(fin_step_a0, fsa0);
+  UP(fin_step_a1, fsa1);
+  UP(fin_step_b0, fsb0);
+  UP(fin_step_b1, fsb1);
+  UP(fin_all_a0, faa0);
+  UP(fin_all_a1, faa1);
+  UP(fin_none, fnone);
+  UP(n_empty, n_empty);
+  UP(zero_empty, fnone);
+  UP(f_vbeg, fvb);
+  UP(f_cbeg, fcb);
+  if (stored > 0) AL(D, (size_t)stored * (size_t)c->ldD);
+  AL(xa, (size_t)n * c->ld);
+  AL(xb, (size_t)n * c->ld);
+  const int64_t rows = std::max<int64_t>(VC + SC, AC);
+  AL(loss_part, (size_t)std::max<int64_t>(rows, 1) * R);
+  AL(unsat_part, (size_t)std::max<int64_t>(rows, 1) * R);
+  AL(bits, (size_t)n * ((R + 63) / 64));
+  AL(best_tmp, F);
+  AL(unsat_tmp, (size_t)F * R);
+  AL(work_counter, 1);
+#undef UP
+#undef AL
+  if ((he = hipStreamSynchronize(s)) != hipSuccess)
+    return create_fail(GALSAT_EDEVICE, std::string("create: ") + hipGetErrorString(he));
+  *out = h.release();
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_destroy(galsat_handle h) {
+  if (!h) return GALSAT_OK;
+  (void)hipDeviceSynchronize();
+  delete h;
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_set_adam_step(galsat_handle h, int32_t t) {
+  GS_CHECK_HANDLE(h);
+  if (t < 0) return h->fail(GALSAT_EINVAL, "adam step must be >= 0");
+  h->adam_t = t;
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_get_info(galsat_handle h, galsat_info* info) {
+  if (!h || !info) return GALSAT_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->num_formulas = h->F;
+  info->n_vars = h->n;
+  info->n_clauses = h->m;
+  info->n_lits = h->L;
+  info->restarts = h->R;
+  info->max_clause_len = h->kmax;
+  info->recompute_max_len = h->krec;
+  info->stored_lits = h->stored;
+  info->schedule = h->schedule;
+  info->lanes_per_item = h->tile.lpi;
+  info->restarts_per_lane = h->tile.rpl;
+  info->var_chunks = h->vch.count();
+  info->clause_chunks = h->sch.count();
+  info->batched_items = 0;
+  info->device_bytes = h->device_bytes;
+  info->adam_step = h->adam_t;
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_init_state(galsat_handle h, float* x, int32_t ldx, uint64_t seed,
+                                           void* stream) {
+  GS_CHECK_HANDLE(h);
+  if (!x && h->n > 0) return h->fail(GALSAT_EINVAL, "x is NULL");
+  if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
+  GS_HIP(h, launch_init_state(x, ldx, h->n, h->R, seed, static_cast<hipStream_t>(stream)), "init_state");
+  return GALSAT_OK;
+}
+
+namespace {
+
+bool aligned_for(const void* p, int32_t ld, int rpl) {
+  if (rpl == 1) return true;
+  return (reinterpret_cast<uintptr_t>(p) % (4 * rpl) == 0) && (ld % rpl == 0);
+}
+
+Tile tile_for(const galsat_ctx* h, const void* a, int32_t lda, const void* b, int32_t ldb) {
+  Tile t = h->tile;
+  if (!aligned_for(a, lda, t.rpl) || (b && !aligned_for(b, ldb, t.rpl))) {
+    t.rpl = 1;
+    t.lpi = std::max(4, std::min(64, pow2_ceil(h->R)));
+  }
+  return t;
+}
+
+VarPassArgs var_args(const galsat_ctx* h) {
+  VarPassArgs a{};
+  a.var_ptr = h->var_ptr;
+  a.var_occ = h->var_occ;
+  a.occ_rec = h->occ_rec;
+  a.clause_ptr = h->clause_ptr;
+  a.clause_lits = h->clause_lits;
+  a.chunk_vbeg = h->vch_beg;
+  a.chunk_vend = h->vch_end;
+  a.var_formula = h->var_formula;
+  a.D = h->D;
+  a.ldD = h->ldD;
+  a.loss_part = h->loss_part;
+  a.unsat_part = h->unsat_part;
+  a.R = h->R;
+  a.lr = h->opt.lr;
+  a.b1 = h->opt.beta1;
+  a.b2 = h->opt.beta2;
+  a.eps = h->opt.eps;
+  return a;
+}
+
+ClausePassArgs stored_clause_args(const galsat_ctx* h) {
+  ClausePassArgs a{};
+  a.clause_ptr = h->clause_ptr;
+  a.clause_lits = h->clause_lits;
+  a.lit_dslot = h->lit_dslot;
+  a.clause_ids = h->stored_ids;
+  a.chunk_cbeg = h->sch_beg;
+  a.chunk_cend = h->sch_end;
+  a.row_base = h->vch.count();
+  a.D = h->D;
+  a.ldD = h->ldD;
+  a.loss_part = h->loss_part;
+  a.unsat_part = h->unsat_part;
+  a.R = h->R;
+  return a;
+}
+
+}  // namespace
+
+extern "C" galsat_status galsat_loss_grad(galsat_handle h, const float* x, int32_t ldx,
+                                          const float* upstream, float* loss, float* grad,
+                                          void* stream) {
+  GS_CHECK_HANDLE(h);
+  if ((!x && h->n > 0) || !loss) return h->fail(GALSAT_EINVAL, "x and loss are required");
+  if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t F = h->F;
+  if (!grad) {
+    // forward only: one clause pass over every clause, nothing stored
+    Tile t = tile_for(h, x, ldx, nullptr, 0);
+    ClausePassArgs a{};
+    a.clause_ptr = h->clause_ptr;
+    a.clause_lits = h->clause_lits;
+    a.clause_ids = nullptr;
+    a.chunk_cbeg = h->ach_beg;
+    a.chunk_cend = h->ach_end;
+    a.row_base = 0;
+    a.x = x;
+    a.ldx = ldx;
+    a.loss_part = h->loss_part;
+    a.unsat_part = h->unsat_part;
+    a.R = h->R;
+    {
+      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
+      GS_HIP(h, launch_clause_pass(a, false, t, h->ach.count(), s), "clause pass");
+    }
+    FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->fin_none, h->fin_none, h->zero_empty,
+                    h->loss_part, h->unsat_part, loss, nullptr, h->R, 0};
+    {
+      ProfScope _ps(h, GALSAT_K_FINALIZE, s);
+      GS_HIP(h, launch_finalize(fa, F, s), "finalize");
+    }
+    return GALSAT_OK;
+  }
+  Tile t = tile_for(h, x, ldx, grad, ldx);
+  if (h->stored > 0) {
+    ClausePassArgs ca = stored_clause_args(h);
+    ca.x = x;
+    ca.ldx = ldx;
+    {
+      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
+      GS_HIP(h, launch_clause_pass(ca, true, t, h->sch.count(), s), "clause pass");
+    }
+  }
+  VarPassArgs va = var_args(h);
+  va.x = x;
+  va.ldx = ldx;
+  va.out = grad;
+  va.ldo = ldx;
+  va.upstream = upstream;
+  {
+    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+    GS_HIP(h, launch_var_pass(va, kModeGrad, t, h->vch.count(), s), "var pass");
+  }
+  FinalizeArgs fa{h->fin_step_a0, h->fin_step_a1, h->fin_step_b0, h->fin_step_b1, h->n_empty,
+                  h->loss_part, h->unsat_part, loss, nullptr, h->R, 0};
+  {
+    ProfScope _ps(h, GALSAT_K_FINALIZE, s);
+    GS_HIP(h, launch_finalize(fa, F, s), "finalize");
+  }
+  return GALSAT_OK;
+}
+
+namespace {
+
+// One general-schedule step from xin to xout (internal layout, ld).
+galsat_status general_step(galsat_ctx* h, Tile t, const float* xin, float* xout, float* mom,
+                           float* vel, int32_t ldm, float* loss_row, int32_t* unsat_row,
+                           hipStream_t s, int f_only) {
+  const int mode = h->opt.optimizer == GALSAT_OPT_ADAM ? kModeAdam : kModeSGD;
+  VarPassArgs va = var_args(h);
+  va.x = xin;
+  va.ldx = h->ld;
+  va.out = xout;
+  va.ldo = h->ld;
+  va.mom = mom;
+  va.vel = vel;
+  va.ldm = ldm;
+  if (mode == kModeAdam) {
+    const int tt = h->adam_t + 1;
+    va.inv_c1 = 1.0 / (1.0 - std::pow((double)h->opt.beta1, tt));
+    va.inv_c2 = 1.0 / (1.0 - std::pow((double)h->opt.beta2, tt));
+  }
+  ClausePassArgs ca = stored_clause_args(h);
+  ca.x = xin;
+  ca.ldx = h->ld;
+  int f0 = 0, f1 = h->F;
+  if (f_only >= 0) { f0 = f_only; f1 = f_only + 1; }
+  const int vc0 = h->vch.f_first[f0], vc1 = h->vch.f_first[f1];
+  const int sc0 = h->sch.f_first[f0], sc1 = h->sch.f_first[f1];
+  if (h->stored > 0 && sc1 > sc0) {
+    ca.chunk_base = sc0;
+    {
+      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
+      GS_HIP(h, launch_clause_pass(ca, true, t, sc1 - sc0, s), "clause pass");
+    }
+  }
+  va.chunk_base = vc0;
+  {
+    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+    GS_HIP(h, launch_var_pass(va, mode, t, vc1 - vc0, s), "var pass");
+  }
+  if (loss_row || unsat_row) {
+    FinalizeArgs fa{h->fin_step_a0, h->fin_step_a1, h->fin_step_b0, h->fin_step_b1, h->n_empty,
+                    h->loss_part, h->unsat_part, loss_row, unsat_row, h->R, f0};
+    {
+      ProfScope _ps(h, GALSAT_K_FINALIZE, s);
+      GS_HIP(h, launch_finalize(fa, f1 - f0, s), "finalize");
+    }
+  }
+  return GALSAT_OK;
+}
+
+}  // namespace
+
+extern "C" galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, float* opt_state,
+                                     int32_t steps, float* loss_trace, int32_t* unsat_trace,
+                                     void* stream) {
+  GS_CHECK_HANDLE(h);
+  if (!x && h->n > 0) return h->fail(GALSAT_EINVAL, "x is NULL");
+  if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
+  if (steps < 0) return h->fail(GALSAT_EINVAL, "steps must be >= 0");
+  const bool adam = h->opt.optimizer == GALSAT_OPT_ADAM;
+  if (adam && !opt_state && h->n > 0) return h->fail(GALSAT_EINVAL, "Adam needs opt_state");
+  if (steps == 0) return GALSAT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t FR = (int64_t)h->F * h->R;
+  float* mom = adam ? opt_state : nullptr;
+  float* vel = adam ? opt_state + (int64_t)h->n * ldx : nullptr;
+  // the internal state is aligned for the planned tile; the caller's Adam
+  // moments may not be
+  const Tile t = adam ? tile_for(h, mom, ldx, vel, ldx) : h->tile;
+  {
+    ProfScope _ps(h, GALSAT_K_COPY, s);
+    GS_HIP(h, launch_copy_state(x, ldx, h->xa, h->ld, h->n, h->R, s), "copy in");
+  }
+  float* cur = h->xa;
+  float* nxt = h->xb;
+  for (int32_t k = 0; k < steps; ++k) {
+    float* lrow = loss_trace ? loss_trace + k * FR : nullptr;
+    int32_t* urow = unsat_trace ? unsat_trace + k * FR : nullptr;
+    if (h->schedule == GALSAT_SCHED_PLAIN) {
+      for (int f = 0; f < h->F; ++f) {
+        galsat_status st = general_step(h, t, cur, nxt, mom, vel, ldx, lrow, urow, s, f);
+        if (st != GALSAT_OK) return st;
+      }
+    } else {
+      galsat_status st = general_step(h, t, cur, nxt, mom, vel, ldx, lrow, urow, s, -1);
+      if (st != GALSAT_OK) return st;
+    }
+    if (adam) h->adam_t++;
+    std::swap(cur, nxt);
+  }
+  {
+    ProfScope _ps(h, GALSAT_K_COPY, s);
+    GS_HIP(h, launch_copy_state(cur, h->ld, x, ldx, h->n, h->R, s), "copy out");
+  }
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_round_check(galsat_handle h, const float* x, int32_t ldx,
+                                            int32_t* unsat, int32_t* best_restart,
+                                            uint8_t* best_assign, void* stream) {
+  GS_CHECK_HANDLE(h);
+  if ((!x && h->n > 0) || !unsat) return h->fail(GALSAT_EINVAL, "x and unsat are required");
+  if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  {
+    ProfScope _ps(h, GALSAT_K_PACK, s);
+    GS_HIP(h, launch_pack_bits(x, ldx, h->n, h->R, h->bits, s), "pack bits");
+  }
+  {
+    ProfScope _ps(h, GALSAT_K_COUNT, s);
+    GS_HIP(h, launch_count_unsat(h->clause_ptr, h->clause_lits, h->ach_beg, h->ach_end, h->ach.count(),
+                                 h->bits, h->n, h->R, h->unsat_part, s),
+           "count unsat");
+  }
+  FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->fin_none, h->fin_none, h->zero_empty,
+                  h->loss_part, h->unsat_part, nullptr, unsat, h->R, 0};
+  {
+    ProfScope _ps(h, GALSAT_K_FINALIZE, s);
+    GS_HIP(h, launch_finalize(fa, h->F, s), "finalize");
+  }
+  if (best_restart || best_assign) {
+    int32_t* best = best_restart ? best_restart : h->best_tmp;
+    {
+      ProfScope _ps(h, GALSAT_K_SELECT, s);
+      GS_HIP(h, launch_best(unsat, h->F, h->R, best, s), "best");
+    }
+    if (best_assign)
+      {
+        ProfScope _ps(h, GALSAT_K_SELECT, s);
+        GS_HIP(h, launch_best_assign(h->bits, h->n, h->var_formula, best, best_assign, s), "best assign");
+      }
+  }
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_profile(galsat_handle h, int32_t enable) {
+  GS_CHECK_HANDLE(h);
+  if (enable) {
+    for (auto& r : h->recs) {
+      (void)hipEventSynchronize(r.b);
+    }
+    h->release_records();
+  }
+  h->prof = enable != 0;
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_kernel_times(galsat_handle h, galsat_kernel_stats* out) {
+  GS_CHECK_HANDLE(h);
+  if (!out) return h->fail(GALSAT_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  for (auto& r : h->recs) {
+    GS_HIP(h, hipEventSynchronize(r.b), "event synchronize");
+    float ms = 0.0f;
+    GS_HIP(h, hipEventElapsedTime(&ms, r.a, r.b), "event elapsed");
+    if (r.kind >= 0 && r.kind < GALSAT_K_KINDS) {
+      out->launches[r.kind] += 1;
+      out->total_ms[r.kind] += ms;
+    }
+  }
+  return GALSAT_OK;
+}

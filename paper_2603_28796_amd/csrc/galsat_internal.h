@@ -1,0 +1,145 @@
+// Internal declarations shared by the host runtime and the kernels of
+// libgalsat.  Not part of the public ABI (include/galsat.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/galsat.h"
+
+namespace galsat {
+
+constexpr int kBlock = 256;  // threads per workgroup of the general passes
+
+// Launch shape of a general pass: each variable (or clause) is handled by
+// `lpi` lanes, each lane covering `rpl` consecutive restarts, so one item
+// covers a restart tile of lpi*rpl restarts; grid.y walks the tiles.
+struct Tile {
+  int lpi = 64;
+  int rpl = 1;
+  int tile() const { return lpi * rpl; }
+};
+
+// Arguments of the variable-parallel pass (backward gather + fused update).
+struct VarPassArgs {
+  const int32_t* var_ptr;
+  const int32_t* var_occ;
+  const int32_t* occ_rec;       // >= 0: clause id to recompute; < 0: -(stored row + 1)
+  const int32_t* clause_ptr;
+  const int32_t* clause_lits;
+  const int32_t* chunk_vbeg;    // [chunks] variable range of each chunk
+  const int32_t* chunk_vend;
+  const int32_t* var_formula;   // [n] formula of each variable (upstream scaling)
+  int32_t chunk_base;           // first chunk of this launch
+  const float* x;
+  int32_t ldx;
+  float* out;                   // next state (update modes) or gradient (grad mode)
+  int32_t ldo;
+  const float* D;               // stored partials [rows][ldD]
+  int64_t ldD;
+  float* mom;                   // Adam first moment [n][ldm]
+  float* vel;                   // Adam second moment [n][ldm]
+  int32_t ldm;
+  const float* upstream;        // grad mode: [F*R] or null
+  double* loss_part;            // [rows][R] partial sums (row = chunk id)
+  int32_t* unsat_part;
+  int32_t R;
+  float lr;
+  float b1, b2, eps;
+  double inv_c1, inv_c2;        // Adam bias corrections 1/(1-b^t)
+};
+
+// Arguments of the clause-parallel pass (forward, and prefix/suffix
+// partials for stored clauses).
+struct ClausePassArgs {
+  const int32_t* clause_ptr;
+  const int32_t* clause_lits;
+  const int32_t* lit_dslot;     // [L] stored row of each literal position
+  const int32_t* clause_ids;    // [list] clause ids, or null for identity
+  const int32_t* chunk_cbeg;    // [chunks] range in the clause list
+  const int32_t* chunk_cend;
+  int32_t chunk_base;
+  int32_t row_base;             // partial row of chunk 0
+  const float* x;
+  int32_t ldx;
+  float* D;
+  int64_t ldD;
+  double* loss_part;
+  int32_t* unsat_part;
+  int32_t R;
+};
+
+struct FinalizeArgs {
+  const int32_t* a_beg;         // [F] partial rows [a_beg, a_end) and [b_beg, b_end)
+  const int32_t* a_end;
+  const int32_t* b_beg;
+  const int32_t* b_end;
+  const int32_t* n_empty;       // [F] empty clauses (U = 1, always unsatisfied)
+  const double* loss_part;
+  const int32_t* unsat_part;
+  float* loss_out;              // [F*R] or null
+  int32_t* unsat_out;           // [F*R] or null
+  int32_t R;
+  int32_t f_base;
+};
+
+enum VarMode { kModeSGD = 0, kModeAdam = 1, kModeGrad = 2 };
+
+// Launchers (galsat_kernels.hip).  All return the launch's hipError_t.
+hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s);
+hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int chunks,
+                              hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, int F, hipStream_t s);
+hipError_t launch_init_state(float* x, int32_t ldx, int32_t n, int32_t R, uint64_t seed,
+                             hipStream_t s);
+hipError_t launch_copy_state(const float* src, int32_t lds, float* dst, int32_t ldd, int32_t n,
+                             int32_t R, hipStream_t s);
+hipError_t launch_pack_bits(const float* x, int32_t ldx, int32_t n, int32_t R, uint64_t* bits,
+                            hipStream_t s);
+hipError_t launch_count_unsat(const int32_t* clause_ptr, const int32_t* clause_lits,
+                              const int32_t* chunk_cbeg, const int32_t* chunk_cend, int chunks,
+                              const uint64_t* bits, int32_t n, int32_t R, int32_t* unsat_part,
+                              hipStream_t s);
+hipError_t launch_best(const int32_t* unsat, int32_t F, int32_t R, int32_t* best, hipStream_t s);
+hipError_t launch_best_assign(const uint64_t* bits, int32_t n, const int32_t* var_formula,
+                              const int32_t* best, uint8_t* out, hipStream_t s);
+
+// Batched schedule: one persistent launch, all steps in-kernel, each work
+// item's state in LDS (galsat_batched.hip).
+struct BatchedArgs {
+  const int32_t* item_formula;   // [items] in launch (LPT) order
+  const int32_t* item_r0;        // first restart of the item
+  const int32_t* item_rcount;    // restarts of the item
+  const int32_t* f_vbeg;         // [F+1]
+  const int32_t* f_cbeg;         // [F+1]
+  const int32_t* var_ptr;
+  const int32_t* var_occ;
+  const int32_t* occ_rec;        // clause id of every occurrence (all recompute)
+  const int32_t* clause_ptr;
+  const int32_t* clause_lits;
+  const int32_t* n_empty;        // [F]
+  float* x;                      // caller state [n][ldx], read at start, written at end
+  int32_t ldx;
+  float* mom;
+  float* vel;
+  int32_t ldm;
+  float* loss_trace;             // [steps][F*R] or null
+  int32_t* unsat_trace;
+  int32_t* work_counter;         // persistent work queue head (zeroed before launch)
+  int32_t items;
+  int32_t steps;
+  int32_t R;
+  int32_t F;
+  int32_t optimizer;
+  float lr, b1, b2, eps;
+  int32_t adam_t0;               // Adam step counter before the first step
+  int32_t lds_floats;            // LDS floats available for state
+};
+
+hipError_t launch_batched(const BatchedArgs& a, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s);
+
+}  // namespace galsat

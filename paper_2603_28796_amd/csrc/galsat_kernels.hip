@@ -1,0 +1,581 @@
+// HIP kernels of the general schedule for gfx950 (MI355X, wave64).
+//
+// Mapping: an item (a variable or a clause) is processed by LPI lanes, each
+// lane owning RPL consecutive restarts, so the restarts of one variable row
+// x[v][r0 .. r0+LPI*RPL) are read and written with contiguous, coalesced
+// accesses while every index of the item is shared by its lanes (with
+// LPI = 64 the whole wave works on one item and the index loads become
+// scalar loads).  All sums run in a fixed order: per-thread in FP64, then
+// across the items of a workgroup in slot order, then across workgroups in
+// chunk order, so every result is bitwise reproducible without atomics.
+//
+// Paper passages: clause value U_t = prod_i (1 - s_i) (Section 3.2, Eq. 2)
+// with the negation rule of Eq. (1); loss' = sum_t U_t (Eq. 5 shifted by
+// the clause count); the gradient is the derivative of that sum
+// (backpropagation through Eq. 2); rounding x_hat = [x > 0.5] is the argmax
+// of Eq. (4) with ties to 0.
+#include "galsat_internal.h"
+
+namespace galsat {
+
+// ---------------------------------------------------------------- helpers
+
+// Clause factor (1 - s) of a literal at variable value xv: a negated
+// literal has s = 1 - xv and factor xv, a positive one factor 1 - xv.
+__device__ __forceinline__ float lit_factor(int code, float xv) {
+  return (code & 1) ? xv : 1.0f - xv;
+}
+
+// Truth of a literal under the rounded assignment [xv > 0.5].
+__device__ __forceinline__ bool lit_true(int code, float xv) {
+  const bool one = xv > 0.5f;
+  return (code & 1) ? !one : one;
+}
+
+template <int N>
+__device__ __forceinline__ void load_row(const float* __restrict__ p, float (&o)[N]) {
+  if constexpr (N == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+  } else if constexpr (N == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    o[0] = t.x; o[1] = t.y;
+  } else {
+    o[0] = p[0];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void store_row(float* __restrict__ p, const float (&o)[N]) {
+  if constexpr (N == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  } else if constexpr (N == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(o[0], o[1]);
+  } else {
+    p[0] = o[0];
+  }
+}
+
+// With a whole wave on one item, item indices are wave-uniform: moving them
+// to a scalar register lets the compiler use scalar loads for the CSR.
+template <int LPI>
+__device__ __forceinline__ int uniform(int v) {
+  if constexpr (LPI == 64) return __builtin_amdgcn_readfirstlane(v);
+  return v;
+}
+
+__device__ __forceinline__ float clamp01(double y) {
+  y = y < 0.0 ? 0.0 : y;
+  y = y > 1.0 ? 1.0 : y;
+  return (float)y;
+}
+
+// Sum per-thread partials over the item slots of the block in slot order
+// and write one row of partial sums per (chunk, restart).
+template <int LPI, int RPL>
+__device__ __forceinline__ void block_partials(const double (&lsum)[RPL], const int (&usum)[RPL],
+                                               int64_t row, int R, double* loss_part,
+                                               int32_t* unsat_part) {
+  constexpr int IPB = kBlock / LPI;
+  constexpr int RT = LPI * RPL;
+  __shared__ double s_l[kBlock * RPL];
+  __shared__ int s_u[kBlock * RPL];
+  const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    s_l[slot * RT + lane * RPL + j] = lsum[j];
+    s_u[slot * RT + lane * RPL + j] = usum[j];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < RT; i += kBlock) {
+    double acc = 0.0;
+    int uacc = 0;
+    for (int s = 0; s < IPB; ++s) {
+      acc += s_l[s * RT + i];
+      uacc += s_u[s * RT + i];
+    }
+    const int r = blockIdx.y * RT + i;
+    if (r < R) {
+      loss_part[row * R + r] = acc;
+      unsat_part[row * R + r] = uacc;
+    }
+  }
+}
+
+// ------------------------------------------------------- variable pass
+//
+// For each variable v of the chunk and each restart r of the lane:
+//   g[v][r] = sum over the occurrences q of v (var_occ order) of
+//             dU_t/dx_v = slope_j * prod_{i != j} factor_i,
+// taking the product over the other literals either from the stored
+// partial row (occ_rec < 0) or by recomputing it from x (occ_rec = t).
+// The occurrence that is the first literal of a recomputed clause also
+// accounts for that clause's U_t and its rounded satisfaction, so each
+// clause enters the loss and the unsat count exactly once.  The epilogue
+// applies the projected SGD or Adam update (writing the next state) or
+// writes the (upstream-scaled) gradient.
+template <int LPI, int RPL, int MODE>
+__global__ __launch_bounds__(kBlock) void k_var_pass(VarPassArgs a) {
+  constexpr int IPB = kBlock / LPI;
+  constexpr int RT = LPI * RPL;
+  const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
+  const int chunk = a.chunk_base + blockIdx.x;
+  const int r0 = blockIdx.y * RT + lane * RPL;
+  const bool active = r0 < a.R;
+  const int vb = a.chunk_vbeg[chunk], ve = a.chunk_vend[chunk];
+  double lsum[RPL];
+  int usum[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) { lsum[j] = 0.0; usum[j] = 0; }
+
+  for (int v0 = vb + slot; v0 < ve; v0 += IPB) {
+    const int v = uniform<LPI>(v0);
+    double g[RPL];
+    float xv[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) { g[j] = 0.0; xv[j] = 0.0f; }
+    if (active) load_row<RPL>(a.x + (int64_t)v * a.ldx + r0, xv);
+    const int qb = a.var_ptr[v], qe = a.var_ptr[v + 1];
+    for (int q = qb; q < qe; ++q) {
+      const int rec = a.occ_rec[q];
+      if (rec < 0) {
+        if (active) {
+          float d[RPL];
+          load_row<RPL>(a.D + (int64_t)(-rec - 1) * a.ldD + r0, d);
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) g[j] += (double)d[j];
+        }
+        continue;
+      }
+      const int p = a.var_occ[q];
+      const int cs = a.clause_ptr[rec], ce = a.clause_ptr[rec + 1];
+      float prod[RPL];
+      bool any_true[RPL];
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) { prod[j] = 1.0f; any_true[j] = false; }
+      for (int i = cs; i < ce; ++i) {
+        if (i == p) continue;
+        const int code = a.clause_lits[i];
+        if (active) {
+          float y[RPL];
+          load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + r0, y);
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) {
+            prod[j] *= lit_factor(code, y[j]);
+            any_true[j] = any_true[j] || lit_true(code, y[j]);
+          }
+        }
+      }
+      const int own = a.clause_lits[p];
+      const float slope = (own & 1) ? 1.0f : -1.0f;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) g[j] += (double)(slope * prod[j]);
+      if (p == cs) {
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          lsum[j] += (double)(lit_factor(own, xv[j]) * prod[j]);
+          usum[j] += (any_true[j] || lit_true(own, xv[j])) ? 0 : 1;
+        }
+      }
+    }
+    if (!active) continue;
+    float o[RPL];
+    if constexpr (MODE == kModeSGD) {
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) o[j] = clamp01((double)xv[j] - (double)a.lr * g[j]);
+    } else if constexpr (MODE == kModeAdam) {
+      float m[RPL], s2[RPL];
+      float* mp = a.mom + (int64_t)v * a.ldm + r0;
+      float* vp = a.vel + (int64_t)v * a.ldm + r0;
+      load_row<RPL>(mp, m);
+      load_row<RPL>(vp, s2);
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        const double mm = (double)a.b1 * (double)m[j] + (1.0 - (double)a.b1) * g[j];
+        const double vv = (double)a.b2 * (double)s2[j] + (1.0 - (double)a.b2) * g[j] * g[j];
+        m[j] = (float)mm;
+        s2[j] = (float)vv;
+        const double step = (double)a.lr * ((double)m[j] * a.inv_c1) /
+                            (sqrt((double)s2[j] * a.inv_c2) + (double)a.eps);
+        o[j] = clamp01((double)xv[j] - step);
+      }
+      store_row<RPL>(mp, m);
+      store_row<RPL>(vp, s2);
+    } else {
+      const int R = a.R;
+      const int f = a.upstream ? a.var_formula[v] : 0;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        const double w = a.upstream ? (double)a.upstream[(int64_t)f * R + r0 + j] : 1.0;
+        o[j] = (float)(w * g[j]);
+      }
+    }
+    store_row<RPL>(a.out + (int64_t)v * a.ldo + r0, o);
+  }
+  block_partials<LPI, RPL>(lsum, usum, chunk, a.R, a.loss_part, a.unsat_part);
+}
+
+// -------------------------------------------------------- clause pass
+//
+// For each clause t of the chunk: U_t = prod_i factor_i, its rounded
+// satisfaction, and (WRITE_D) the partial of every literal j,
+//   D[slot(j)][r] = slope_j * prod_{i<j} factor_i * prod_{i>j} factor_i,
+// from a forward prefix sweep (prefix stored in place) and a backward
+// suffix sweep.  No division: exact zero factors need no special case.
+template <int LPI, int RPL, bool WRITE_D>
+__global__ __launch_bounds__(kBlock) void k_clause_pass(ClausePassArgs a) {
+  constexpr int IPB = kBlock / LPI;
+  constexpr int RT = LPI * RPL;
+  const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
+  const int chunk = a.chunk_base + blockIdx.x;
+  const int r0 = blockIdx.y * RT + lane * RPL;
+  const bool active = r0 < a.R;
+  const int cb = a.chunk_cbeg[chunk], ce = a.chunk_cend[chunk];
+  double lsum[RPL];
+  int usum[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) { lsum[j] = 0.0; usum[j] = 0; }
+
+  for (int c0 = cb + slot; c0 < ce; c0 += IPB) {
+    const int t = uniform<LPI>(a.clause_ids ? a.clause_ids[c0] : c0);
+    const int s = a.clause_ptr[t], e = a.clause_ptr[t + 1];
+    float pre[RPL];
+    bool any_true[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) { pre[j] = 1.0f; any_true[j] = false; }
+    for (int i = s; i < e; ++i) {
+      const int code = a.clause_lits[i];
+      if (active) {
+        float y[RPL];
+        load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + r0, y);
+        if constexpr (WRITE_D) store_row<RPL>(a.D + (int64_t)a.lit_dslot[i] * a.ldD + r0, pre);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          pre[j] *= lit_factor(code, y[j]);
+          any_true[j] = any_true[j] || lit_true(code, y[j]);
+        }
+      }
+    }
+    if (!active) continue;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      lsum[j] += (double)pre[j];
+      usum[j] += any_true[j] ? 0 : 1;
+    }
+    if constexpr (WRITE_D) {
+      float suf[RPL];
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) suf[j] = 1.0f;
+      for (int i = e - 1; i >= s; --i) {
+        const int code = a.clause_lits[i];
+        float y[RPL], d[RPL];
+        load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + r0, y);
+        float* dp = a.D + (int64_t)a.lit_dslot[i] * a.ldD + r0;
+        load_row<RPL>(dp, d);
+        const float slope = (code & 1) ? 1.0f : -1.0f;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          d[j] = slope * (d[j] * suf[j]);
+          suf[j] *= lit_factor(code, y[j]);
+        }
+        store_row<RPL>(dp, d);
+      }
+    }
+  }
+  block_partials<LPI, RPL>(lsum, usum, (int64_t)a.row_base + chunk, a.R, a.loss_part,
+                           a.unsat_part);
+}
+
+// ------------------------------------------------------------ finalize
+//
+// loss[f][r] = sum of the formula's partial rows (fixed order) + empty
+// clauses; the same for the unsat count.
+__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a) {
+  const int f = a.f_base + blockIdx.x;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int r = blockIdx.y * 64 + lane;
+  const int R = a.R;
+  double acc = 0.0;
+  int uacc = 0;
+  if (r < R) {
+    for (int row = a.a_beg[f] + w; row < a.a_end[f]; row += 4) {
+      if (a.loss_out) acc += a.loss_part[(int64_t)row * R + r];
+      if (a.unsat_out) uacc += a.unsat_part[(int64_t)row * R + r];
+    }
+    for (int row = a.b_beg[f] + w; row < a.b_end[f]; row += 4) {
+      if (a.loss_out) acc += a.loss_part[(int64_t)row * R + r];
+      if (a.unsat_out) uacc += a.unsat_part[(int64_t)row * R + r];
+    }
+  }
+  __shared__ double sl[256];
+  __shared__ int su[256];
+  sl[threadIdx.x] = acc;
+  su[threadIdx.x] = uacc;
+  __syncthreads();
+  if (w == 0 && r < R) {
+    const double tot = ((sl[lane] + sl[64 + lane]) + (sl[128 + lane] + sl[192 + lane])) +
+                       (double)a.n_empty[f];
+    const int utot = su[lane] + su[64 + lane] + su[128 + lane] + su[192 + lane] + a.n_empty[f];
+    if (a.loss_out) a.loss_out[(int64_t)f * R + r] = (float)tot;
+    if (a.unsat_out) a.unsat_out[(int64_t)f * R + r] = utot;
+  }
+}
+
+// ---------------------------------------------------------- init / copy
+
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_init_state(float* x, int32_t ldx, int32_t n, int32_t R,
+                                                    uint64_t seed) {
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int r = blockIdx.y * 64 + lane;
+  if (r >= R) return;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + w; v < n; v += (int64_t)gridDim.x * 4) {
+    const uint64_t key = ((uint64_t)(uint32_t)v << 32) + (uint64_t)(uint32_t)r + 0x9e3779b97f4a7c15ULL;
+    const uint64_t h = splitmix_mix(seed ^ splitmix_mix(key));
+    x[v * ldx + r] = (float)(h >> 40) * (1.0f / 16777216.0f);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_copy_state(const float* src, int32_t lds, float* dst,
+                                                    int32_t ldd, int32_t n, int32_t R) {
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int r = blockIdx.y * 64 + lane; r < R; r += gridDim.y * 64)
+    for (int64_t v = (int64_t)blockIdx.x * 4 + w; v < n; v += (int64_t)gridDim.x * 4)
+      dst[v * ldd + r] = src[v * lds + r];
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// ------------------------------------------------------- round & count
+//
+// bits[w][v]: bit l = [x[v][64w + l] > 0.5] packed by one wavefront ballot.
+__global__ __launch_bounds__(256) void k_pack_bits(const float* x, int32_t ldx, int32_t n,
+                                                   int32_t R, uint64_t* bits) {
+  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int word = blockIdx.y;
+  const int r = word * 64 + lane;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + wv; v < n; v += (int64_t)gridDim.x * 4) {
+    const bool one = (r < R) && (x[v * ldx + r] > 0.5f);
+    const uint64_t m = __ballot(one);
+    if (lane == 0) bits[(int64_t)word * n + v] = m;
+  }
+}
+
+// Lanes take one clause each; for the 64 restarts of word w a clause's
+// "unsatisfied" mask is the AND over its literals of "literal false".  The
+// per-restart count over the wave's 64 clauses is then one ballot and one
+// popcount per restart, accumulated by the lane that owns the restart.
+__global__ __launch_bounds__(256) void k_count_unsat(const int32_t* clause_ptr,
+                                                     const int32_t* clause_lits,
+                                                     const int32_t* chunk_cbeg,
+                                                     const int32_t* chunk_cend,
+                                                     const uint64_t* bits, int32_t n, int32_t R,
+                                                     int32_t* unsat_part) {
+  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int chunk = blockIdx.x, word = blockIdx.y;
+  const int cb = chunk_cbeg[chunk], ce = chunk_cend[chunk];
+  const int rem = R - word * 64;
+  const uint64_t valid = rem >= 64 ? ~0ULL : ((1ULL << rem) - 1ULL);
+  const uint64_t* bw = bits + (int64_t)word * n;
+  int cnt = 0;
+  for (int base = cb + wv * 64; base < ce; base += 256) {
+    const int t = base + lane;
+    uint64_t mask = 0;
+    if (t < ce) {
+      mask = valid;
+      for (int p = clause_ptr[t]; p < clause_ptr[t + 1]; ++p) {
+        const int code = clause_lits[p];
+        const uint64_t b = bw[code >> 1];
+        const uint64_t lit_is_true = (code & 1) ? ~b : b;
+        mask &= ~lit_is_true;
+      }
+    }
+    for (int j = 0; j < 64; ++j) {
+      const uint64_t bal = __ballot((mask >> j) & 1ULL);
+      if (lane == j) cnt += __popcll(bal);
+    }
+  }
+  __shared__ int s[256];
+  s[threadIdx.x] = cnt;
+  __syncthreads();
+  if (wv == 0) {
+    const int r = word * 64 + lane;
+    if (r < R) unsat_part[(int64_t)chunk * R + r] = s[lane] + s[64 + lane] + s[128 + lane] + s[192 + lane];
+  }
+}
+
+// best[f] = argmin_r unsat[f][r], ties to the lowest r, via the packed key
+// (unsat << 32) | r.
+__global__ __launch_bounds__(256) void k_best(const int32_t* unsat, int32_t R, int32_t* best) {
+  const int f = blockIdx.x;
+  uint64_t key = ~0ULL;
+  for (int r = threadIdx.x; r < R; r += 256) {
+    const uint64_t k = ((uint64_t)(uint32_t)unsat[(int64_t)f * R + r] << 32) | (uint32_t)r;
+    key = k < key ? k : key;
+  }
+  __shared__ uint64_t s[256];
+  s[threadIdx.x] = key;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] = s[threadIdx.x + w] < s[threadIdx.x] ? s[threadIdx.x + w] : s[threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) best[f] = (int32_t)(s[0] & 0xffffffffULL);
+}
+
+__global__ void k_best_assign(const uint64_t* bits, int32_t n, const int32_t* var_formula,
+                              const int32_t* best, uint8_t* out) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int r = best[var_formula[v]];
+    out[v] = (uint8_t)((bits[(int64_t)(r >> 6) * n + v] >> (r & 63)) & 1ULL);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+namespace {
+
+template <int LPI, int RPL>
+hipError_t var_pass_rpl(const VarPassArgs& a, int mode, int chunks, int tiles, hipStream_t s) {
+  dim3 grid(chunks, tiles), block(kBlock);
+  switch (mode) {
+    case kModeSGD: hipLaunchKernelGGL((k_var_pass<LPI, RPL, kModeSGD>), grid, block, 0, s, a); break;
+    case kModeAdam: hipLaunchKernelGGL((k_var_pass<LPI, RPL, kModeAdam>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_var_pass<LPI, RPL, kModeGrad>), grid, block, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <int LPI>
+hipError_t var_pass_lpi(const VarPassArgs& a, int mode, Tile t, int chunks, int tiles, hipStream_t s) {
+  switch (t.rpl) {
+    case 4: return var_pass_rpl<LPI, 4>(a, mode, chunks, tiles, s);
+    case 2: return var_pass_rpl<LPI, 2>(a, mode, chunks, tiles, s);
+    default: return var_pass_rpl<LPI, 1>(a, mode, chunks, tiles, s);
+  }
+}
+
+template <int LPI, int RPL>
+hipError_t clause_pass_rpl(const ClausePassArgs& a, bool write_d, int chunks, int tiles, hipStream_t s) {
+  dim3 grid(chunks, tiles), block(kBlock);
+  if (write_d) hipLaunchKernelGGL((k_clause_pass<LPI, RPL, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_clause_pass<LPI, RPL, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <int LPI>
+hipError_t clause_pass_lpi(const ClausePassArgs& a, bool write_d, Tile t, int chunks, int tiles,
+                           hipStream_t s) {
+  switch (t.rpl) {
+    case 4: return clause_pass_rpl<LPI, 4>(a, write_d, chunks, tiles, s);
+    case 2: return clause_pass_rpl<LPI, 2>(a, write_d, chunks, tiles, s);
+    default: return clause_pass_rpl<LPI, 1>(a, write_d, chunks, tiles, s);
+  }
+}
+
+inline int grid_x_for(int64_t items_div4) {
+  int64_t g = items_div4 < 1 ? 1 : items_div4;
+  return (int)(g > 65536 ? 65536 : g);
+}
+
+}  // namespace
+
+hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s) {
+  if (chunks <= 0) return hipSuccess;
+  const int tiles = (a.R + t.tile() - 1) / t.tile();
+  switch (t.lpi) {
+    case 4: return var_pass_lpi<4>(a, mode, t, chunks, tiles, s);
+    case 8: return var_pass_lpi<8>(a, mode, t, chunks, tiles, s);
+    case 16: return var_pass_lpi<16>(a, mode, t, chunks, tiles, s);
+    case 32: return var_pass_lpi<32>(a, mode, t, chunks, tiles, s);
+    default: return var_pass_lpi<64>(a, mode, t, chunks, tiles, s);
+  }
+}
+
+hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int chunks,
+                              hipStream_t s) {
+  if (chunks <= 0) return hipSuccess;
+  const int tiles = (a.R + t.tile() - 1) / t.tile();
+  switch (t.lpi) {
+    case 4: return clause_pass_lpi<4>(a, write_d, t, chunks, tiles, s);
+    case 8: return clause_pass_lpi<8>(a, write_d, t, chunks, tiles, s);
+    case 16: return clause_pass_lpi<16>(a, write_d, t, chunks, tiles, s);
+    case 32: return clause_pass_lpi<32>(a, write_d, t, chunks, tiles, s);
+    default: return clause_pass_lpi<64>(a, write_d, t, chunks, tiles, s);
+  }
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, int F, hipStream_t s) {
+  if (F <= 0) return hipSuccess;
+  dim3 grid(F, (a.R + 63) / 64), block(256);
+  hipLaunchKernelGGL(k_finalize, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(float* x, int32_t ldx, int32_t n, int32_t R, uint64_t seed,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(grid_x_for(((int64_t)n + 3) / 4), (R + 63) / 64), block(256);
+  hipLaunchKernelGGL(k_init_state, grid, block, 0, s, x, ldx, n, R, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_state(const float* src, int32_t lds, float* dst, int32_t ldd, int32_t n,
+                             int32_t R, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int gy = (R + 63) / 64 > 64 ? 64 : (R + 63) / 64;
+  dim3 grid(grid_x_for(((int64_t)n + 3) / 4), gy), block(256);
+  hipLaunchKernelGGL(k_copy_state, grid, block, 0, s, src, lds, dst, ldd, n, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_x_for((count + 255) / 256)), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_bits(const float* x, int32_t ldx, int32_t n, int32_t R, uint64_t* bits,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(grid_x_for(((int64_t)n + 3) / 4), (R + 63) / 64), block(256);
+  hipLaunchKernelGGL(k_pack_bits, grid, block, 0, s, x, ldx, n, R, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_unsat(const int32_t* clause_ptr, const int32_t* clause_lits,
+                              const int32_t* chunk_cbeg, const int32_t* chunk_cend, int chunks,
+                              const uint64_t* bits, int32_t n, int32_t R, int32_t* unsat_part,
+                              hipStream_t s) {
+  if (chunks <= 0) return hipSuccess;
+  dim3 grid(chunks, (R + 63) / 64), block(256);
+  hipLaunchKernelGGL(k_count_unsat, grid, block, 0, s, clause_ptr, clause_lits, chunk_cbeg,
+                     chunk_cend, bits, n, R, unsat_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_best(const int32_t* unsat, int32_t F, int32_t R, int32_t* best, hipStream_t s) {
+  if (F <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_best, dim3(F), dim3(256), 0, s, unsat, R, best);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_assign(const uint64_t* bits, int32_t n, const int32_t* var_formula,
+                              const int32_t* best, uint8_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_best_assign, dim3(grid_x_for(((int64_t)n + 255) / 256)), dim3(256), 0, s,
+                     bits, n, var_formula, best, out);
+  return hipGetLastError();
+}
+
+}  // namespace galsat

@@ -1,0 +1,131 @@
+"""The C ABI library loads and exports every symbol include/galsat.h declares;
+host-side validation rejects malformed problems before touching the device
+(these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_28796_amd import galsat as G
+from paper_2603_28796_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "galsat.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(galsat_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(G.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = G.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_defaults():
+    lib = G.load_library()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.galsat_status_string(code)
+    opt = G._Options()
+    lib.galsat_default_options(ctypes.byref(opt))
+    assert opt.optimizer == 0 and abs(opt.lr - 0.1) < 1e-7
+    assert abs(opt.beta1 - 0.9) < 1e-7 and abs(opt.beta2 - 0.999) < 1e-7
+    assert opt.validate == 1 and opt.partials == 0 and opt.schedule == 0
+
+
+def _create(cnf, R=4, **over):
+    lib = G.load_library()
+    arrs = {k: np.ascontiguousarray(getattr(cnf, k), dtype=np.int32) for k in
+            ("formula_var_begin", "formula_clause_begin", "clause_ptr", "clause_lits", "var_ptr",
+             "var_occ")}
+    arrs.update({k: np.ascontiguousarray(v, dtype=np.int32) for k, v in over.items()
+                 if isinstance(v, np.ndarray)})
+    F = over.get("F", cnf.F)
+    n = over.get("n", cnf.n)
+    m = over.get("m", cnf.m)
+    L = over.get("L", cnf.L)
+    nul = over.get("null", ())
+    prob = G._Problem(F, None if "fvb" in nul else arrs["formula_var_begin"].ctypes.data,
+                      None if "fcb" in nul else arrs["formula_clause_begin"].ctypes.data, n, m, L,
+                      arrs["clause_ptr"].ctypes.data, arrs["clause_lits"].ctypes.data,
+                      arrs["var_ptr"].ctypes.data, arrs["var_occ"].ctypes.data, R, 0)
+    h = ctypes.c_void_p()
+    st = lib.galsat_create(ctypes.byref(prob), None, None, ctypes.byref(h))
+    return st, lib.galsat_last_error(None).decode(), h
+
+
+@pytest.fixture
+def small():
+    return I.from_clauses([[1, -2, 3], [-1, 2], [2, 3, -4], [4]], n=4)
+
+
+def test_rejects_bad_clause_ptr(small):
+    cp = small.clause_ptr.copy()
+    cp[2] = cp[1] - 1
+    st, msg, h = _create(small, clause_ptr=cp)
+    assert st == -1 and "clause_ptr" in msg and not h.value
+
+
+def test_rejects_literal_out_of_range(small):
+    cl = small.clause_lits.copy()
+    cl[0] = 2 * small.n + 1
+    st, msg, _ = _create(small, clause_lits=cl)
+    assert st == -1 and "out of range" in msg
+
+
+def test_rejects_non_transpose(small):
+    vo = small.var_occ.copy()
+    vo[0], vo[-1] = vo[-1], vo[0]
+    st, msg, _ = _create(small, var_occ=vo)
+    assert st == -1 and "transpose" in msg
+
+
+def test_rejects_duplicate_occurrence():
+    cnf = I.from_clauses([[1, 2], [1, 3]], n=3)
+    vo = cnf.var_occ.copy()
+    # variable 0 occurs at positions 0 and 2; list position 0 twice
+    assert vo[0] == 0 and vo[1] == 2
+    vo[1] = 0
+    st, msg, _ = _create(cnf, var_occ=vo)
+    assert st == -1 and ("twice" in msg or "transpose" in msg)
+
+
+def test_rejects_cross_formula_literal():
+    a = I.from_clauses([[1, 2]], n=2)
+    b = I.from_clauses([[1, -2]], n=2)
+    batch = I.concat([a, b])
+    cl = batch.clause_lits.copy()
+    cl[0] = 2 * 3  # variable 3 belongs to formula 1
+    vp, vo = I.transpose(2, batch.formula_var_begin.astype(np.int64),
+                         batch.formula_clause_begin.astype(np.int64), batch.clause_ptr, cl)
+    st, msg, _ = _create(batch, clause_lits=cl, var_ptr=vp, var_occ=vo)
+    assert st == -1 and "another formula" in msg
+
+
+def test_rejects_missing_formula_ranges():
+    batch = I.concat([I.from_clauses([[1]], n=1), I.from_clauses([[-1]], n=1)])
+    st, msg, _ = _create(batch, null=("fvb", "fcb"))
+    assert st == -1 and "formula" in msg
+
+
+def test_rejects_bad_sizes(small):
+    st, _, _ = _create(small, R=0)
+    assert st == -1
+    st, _, _ = _create(small, F=0)
+    assert st == -1
+    st, msg, _ = _create(small, L=small.L - 1)
+    assert st == -1
+
+
+def test_python_binding_fails_loudly_without_library(tmp_path):
+    with pytest.raises(RuntimeError, match="not found"):
+        G.load_library(str(tmp_path / "missing.so"))

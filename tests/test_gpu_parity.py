@@ -1,0 +1,267 @@
+"""GPU parity of libgalsat against the FP64 oracle (through the C ABI).
+
+Every case evaluates the HIP path and the oracle at the same state: loss,
+gradient, rounded unsat counts, the hand-off selection, and one update
+step checked against the oracle's update of the same state and gradient.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_28796_amd import inputs as I
+from paper_2603_28796_amd.galsat import Problem, GalsatLoss
+from tests.gpu_util import (check_counts, check_grad, check_loss, check_update, parity_at, say,
+                            to_oracle, from_oracle)
+
+pytestmark = pytest.mark.gpu
+
+
+def _x0(n, R, seed, ld=None):
+    rng = np.random.default_rng(seed)
+    return from_oracle(rng.random((R, n)), ld)
+
+
+def _edge_formula():
+    clauses = [
+        [1, -2, 3], [-1], [2, 2, -5], [4, -4], [], [6, 7, 8, 9, 10, 11, 12],
+        [-3, -6], [5], [], [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18],
+        [13, -13, 14], [-14, -15, -16, -17],
+    ]
+    # a long clause of 60 distinct literals and a variable (id 99) in no clause
+    clauses.append([((i * 7) % 90) + 1 if i % 2 else -(((i * 7) % 90) + 1) for i in range(60)])
+    return I.from_clauses(clauses, n=100, name="edge")
+
+
+def _batch():
+    fs = [I.planted_ksat(20 + 13 * i, int((20 + 13 * i) * 4.0), 3, seed=300 + i) for i in range(12)]
+    fs.append(I.from_clauses([[]], n=1))                    # one empty clause
+    fs.append(I.structured_mixed(n=2000, m=8000, n_comm=10, seed=77))
+    fs.append(I.from_clauses([[1, 2], [-1, 2], [1, -2], [-1, -2]], n=2))  # UNSAT
+    return I.concat(fs, name="batch")
+
+
+CASES = {
+    "planted300": lambda: I.planted_ksat(300, 1278, 3, seed=11),
+    "mixed20k": lambda: I.structured_mixed(n=20000, m=80000, n_comm=20, seed=12),
+    "edge": _edge_formula,
+    "batch": _batch,
+    "long_mix": lambda: I.generate(I.spec(2, k0=3, ka=50, kb=200, p0=0.9, var_kind=1, zipf_s=1.2),
+                                   13, [5000], [6000], "long_mix"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("R", [1, 3, 16, 64, 100])
+@pytest.mark.parametrize("partials", ["recompute", "store", "auto"])
+def test_parity_cases(case, R, partials):
+    say(f"[parity] case={case} R={R} partials={partials}")
+    cnf = CASES[case]()
+    prob = Problem(cnf, R, partials=partials, lr=0.1)
+    x = _x0(cnf.n, R, seed=R)
+    parity_at(prob, cnf, x, f"{case}/R={R}/{partials}")
+    # one fused step: compare with the oracle's update of the same state
+    xr = to_oracle(x, R)
+    _, g_gpu = prob.loss_grad(x)
+    g_gpu64 = to_oracle(g_gpu, R)
+    lo_ref, g_ref, A = oracle.grad(cnf, xr, with_abs=True)
+    x1 = x.clone()
+    lt, ut = prob.step(x1, 1, trace=True)
+    torch.cuda.synchronize()
+    check_loss(lt[0], lo_ref, cnf, "step trace")
+    check_counts(ut[0], oracle.unsat(cnf, xr), "step trace")
+    lr = prob.lr
+    check_update(x1, oracle.step_sgd(xr, g_gpu64, lr), xr, R, "update vs GPU gradient")
+    # against the oracle's own gradient the step error is bounded by lr * gradient tolerance
+    err = np.abs(to_oracle(x1, R) - oracle.step_sgd(xr, g_ref, lr))
+    assert np.all(err <= lr * 1e-5 * (np.abs(g_ref) + A) + 2.0 ** -24 + 1e-30)
+
+
+@pytest.mark.parametrize("lpi", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("rpl", [1, 2, 4])
+def test_tile_overrides(lpi, rpl):
+    say(f"[tiles] lpi={lpi} rpl={rpl}")
+    cnf = CASES["edge"]()
+    R = 40
+    prob = Problem(cnf, R, partials="auto", recompute_max_len=4, plan_override=f"lpi={lpi},rpl={rpl}")
+    parity_at(prob, cnf, _x0(cnf.n, R, 5), f"lpi={lpi} rpl={rpl}")
+
+
+def test_unaligned_and_padded_state():
+    say("[layout] padded and odd row strides")
+    cnf = CASES["planted300"]()
+    R = 24
+    for ld in (24, 25, 32, 37):
+        prob = Problem(cnf, R)
+        x = _x0(cnf.n, R, 9, ld=ld)
+        parity_at(prob, cnf, x, f"ld={ld}")
+        pad = x[:, R:].clone()
+        prob.step(x, 2)
+        torch.cuda.synchronize()
+        assert torch.equal(x[:, R:], pad), "padding columns must not be written"
+
+
+def test_upstream_scaling():
+    say("[upstream]")
+    cnf = CASES["batch"]()
+    R = 8
+    prob = Problem(cnf, R)
+    up = torch.randn(cnf.F, R, device="cuda")
+    parity_at(prob, cnf, _x0(cnf.n, R, 21), "upstream", upstream=up)
+
+
+def test_init_state_bit_exact():
+    say("[init]")
+    cnf = CASES["planted300"]()
+    for R, ld in ((64, 64), (13, 16)):
+        prob = Problem(cnf, R)
+        x = prob.init_state(0x6A150001, torch.zeros((cnf.n, ld), device="cuda"))
+        torch.cuda.synchronize()
+        ref = oracle.init_state(0x6A150001, cnf.n, R)
+        assert np.array_equal(to_oracle(x, R), ref)
+
+
+def test_planted3sat_n200_every_step():
+    """Planted 3-SAT n=200, m=852, R=64, 500 projected-SGD steps at lr 0.1:
+    loss, gradient and unsat counts per restart at every step, and every
+    update, against the oracle evaluated at the GPU's state."""
+    say("[trajectory] planted3sat n=200 R=64 500 steps")
+    w = I.WORKLOADS["planted3sat_n200"]
+    cnf = w.make()
+    R = w.restarts
+    prob = Problem(cnf, R, lr=w.lr)
+    x = prob.init_state(I.SEED_BASE + 1)
+    lr = prob.lr
+    solved = None
+    for k in range(w.steps):
+        xr = to_oracle(x, R)
+        lo_ref, g_ref, A = oracle.grad(cnf, xr, with_abs=True)
+        _, g = prob.loss_grad(x)
+        x1 = x.clone()
+        lt, ut = prob.step(x1, 1, trace=True)
+        torch.cuda.synchronize()
+        check_loss(lt[0], lo_ref, cnf, f"step {k}")
+        check_counts(ut[0], oracle.unsat(cnf, xr), f"step {k}")
+        check_grad(g, g_ref, A, R, f"step {k}")
+        check_update(x1, oracle.step_sgd(xr, to_oracle(g, R), lr), xr, R, f"step {k}")
+        x = x1
+        if solved is None and (ut[0] == 0).any():
+            solved = k
+    unsat, best, assign = prob.round_check(x)
+    torch.cuda.synchronize()
+    check_counts(unsat, oracle.unsat(cnf, to_oracle(x, R)), "final")
+    say(f"  first restart with 0 unsat at step {solved}; final min unsat {int(unsat.min())}")
+
+
+def test_multi_step_matches_single_steps():
+    """steps=K in one call equals K calls of one step (same kernels, same order)."""
+    say("[multistep]")
+    cnf = CASES["mixed20k"]()
+    R = 32
+    prob = Problem(cnf, R)
+    xa = _x0(cnf.n, R, 31)
+    xb = xa.clone()
+    la, ua = prob.step(xa, 5, trace=True)
+    lb = []
+    for _ in range(5):
+        l1, _ = prob.step(xb, 1, trace=True)
+        lb.append(l1[0])
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb)
+    assert torch.equal(la, torch.stack(lb))
+
+
+def test_determinism_bitwise():
+    say("[determinism]")
+    cnf = CASES["long_mix"]()
+    R = 48
+    outs = []
+    for _ in range(2):
+        prob = Problem(cnf, R, partials="auto")
+        x = _x0(cnf.n, R, 41)
+        loss, g = prob.loss_grad(x)
+        lt, ut = prob.step(x, 3, trace=True)
+        torch.cuda.synchronize()
+        outs.append((loss.clone(), g.clone(), x.clone(), lt.clone(), ut.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_restart_permutation():
+    say("[permutation]")
+    cnf = CASES["planted300"]()
+    R = 64
+    prob = Problem(cnf, R)
+    x = _x0(cnf.n, R, 51)
+    perm = torch.randperm(R, generator=torch.Generator().manual_seed(0)).cuda()
+    loss, g = prob.loss_grad(x)
+    loss_p, g_p = prob.loss_grad(x[:, perm].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(loss_p, loss[:, perm])
+    assert torch.equal(g_p, g[:, perm])
+
+
+def test_adam_teacher_forced():
+    say("[adam]")
+    cnf = CASES["mixed20k"]()
+    R = 16
+    prob = Problem(cnf, R, optimizer="adam", lr=0.5)
+    x = _x0(cnf.n, R, 61)
+    st = prob.new_opt_state(x)
+    b1, b2, eps = float(np.float32(0.9)), float(np.float32(0.999)), float(np.float32(1e-8))
+    for t in range(1, 4):
+        xr = to_oracle(x, R)
+        m0, v0 = to_oracle(st[0], R), to_oracle(st[1], R)
+        _, g = prob.loss_grad(x)
+        prob.step(x, 1, opt_state=st)
+        torch.cuda.synchronize()
+        g64 = to_oracle(g, R)
+        x_ref, m_ref, v_ref = oracle.step_adam(xr, m0, v0, g64, t, lr=prob.lr, b1=b1, b2=b2, eps=eps)
+        # the kernel updates the moments from its FP64 gradient, the oracle from
+        # the FP32-rounded one: bound the difference by the magnitudes summed
+        # (m can cancel) and carry it through the step
+        scale_m = b1 * np.abs(m0) + (1 - b1) * np.abs(g64)
+        assert np.all(np.abs(to_oracle(st[0], R) - m_ref) <= 1e-6 * scale_m + 1e-30)
+        assert np.all(np.abs(to_oracle(st[1], R) - v_ref) <= 1e-6 * v_ref + 1e-30)
+        c1, c2 = 1 - b1 ** t, 1 - b2 ** t
+        slack = prob.lr * 1e-6 * scale_m / c1 / (np.sqrt(v_ref / c2) + eps)
+        err = np.abs(to_oracle(x, R) - x_ref)
+        assert np.all(err <= 1e-5 * np.abs(x_ref - xr) + slack + 2.0 ** -24), f"adam t={t}"
+    assert prob.info()["adam_step"] == 3
+
+
+def test_autograd_function():
+    say("[autograd]")
+    cnf = CASES["batch"]()
+    R = 12
+    prob = Problem(cnf, R)
+    x = _x0(cnf.n, R, 71).requires_grad_(True)
+    loss = GalsatLoss.apply(x, prob)
+    wts = torch.rand(cnf.F, R, device="cuda")
+    (loss * wts).sum().backward()
+    torch.cuda.synchronize()
+    xr = to_oracle(x.detach(), R)
+    lo_ref, g_ref, A = oracle.grad(cnf, xr, with_abs=True)
+    check_loss(loss.detach(), lo_ref, cnf, "autograd forward")
+    w = wts.cpu().numpy().astype(np.float64)[cnf.formula_of_var(), :].T
+    check_grad(x.grad, g_ref * w, A * np.abs(w), R, "autograd backward")
+
+
+def test_round_check_ties_and_exact_points():
+    say("[round]")
+    cnf = CASES["mixed20k"]()
+    R = 130
+    prob = Problem(cnf, R)
+    rng = np.random.default_rng(81)
+    xr = rng.random((R, cnf.n))
+    xr[:, ::5] = 0.5
+    xr[:, 1::7] = 0.0
+    xr[:, 2::7] = 1.0
+    xr[3] = cnf.planted
+    x = from_oracle(xr)
+    unsat, best, assign = prob.round_check(x)
+    torch.cuda.synchronize()
+    ref = oracle.unsat(cnf, to_oracle(x, R))
+    check_counts(unsat, ref)
+    assert int(unsat[0, 3]) == 0
+    assert int(best[0]) == int(oracle.best(ref)[0])
