@@ -7,12 +7,16 @@
 // workspace.  The per-call entry points only enqueue kernels on the
 // caller's stream.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "galsat_internal.h"
@@ -33,6 +37,38 @@ inline int pow2_ceil(int v) {
   while (p < v) p <<= 1;
   return p;
 }
+
+// Runs fn(begin, end) over [0, count) split across host threads (the
+// O(L) validation and planning of galsat_create).
+template <class Fn>
+void parallel_for(int64_t count, Fn fn) {
+  int threads = (int)std::thread::hardware_concurrency();
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) threads = std::max(1, std::atoi(e));
+  threads = std::max(1, std::min(threads, 64));
+  if (count < (1 << 16) || threads == 1) {
+    fn((int64_t)0, count);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int i = 0; i < threads; ++i)
+    pool.emplace_back(fn, count * i / threads, count * (i + 1) / threads);
+  for (auto& t : pool) t.join();
+}
+
+// First error found by concurrent checks: the one at the lowest index wins,
+// so the message does not depend on thread timing.
+struct FirstError {
+  std::mutex mu;
+  int64_t index = -1;
+  std::string msg;
+  void report(int64_t i, const std::string& m) {
+    std::lock_guard<std::mutex> g(mu);
+    if (index < 0 || i < index) {
+      index = i;
+      msg = m;
+    }
+  }
+};
 
 // Work chunks over per-formula item ranges: consecutive items with total
 // cost <= target, never crossing a formula boundary.
@@ -91,15 +127,22 @@ struct galsat_ctx {
 
   std::vector<int32_t> h_fvb, h_fcb;
   Chunks vch, sch, ach;  // var chunks, stored-clause chunks, all-clause chunks
+  Chunks segch;          // chunks of segments of split variables
+  std::vector<int32_t> heavy_f_first;  // [F+1] split variables of each formula
+  int32_t n_heavy = 0, n_seg = 0, step_rows = 0;
 
   // device tables
   int32_t *clause_ptr = nullptr, *clause_lits = nullptr, *var_ptr = nullptr, *var_occ = nullptr;
-  int32_t *occ_rec = nullptr, *lit_dslot = nullptr, *var_formula = nullptr, *stored_ids = nullptr;
-  int32_t *vch_beg = nullptr, *vch_end = nullptr, *sch_beg = nullptr, *sch_end = nullptr;
+  int4* occ4 = nullptr;
+  int32_t *lit_dslot = nullptr, *var_formula = nullptr, *stored_ids = nullptr;
+  int32_t *vch_beg = nullptr, *vch_end = nullptr, *vch_row = nullptr;
+  int32_t *sch_beg = nullptr, *sch_end = nullptr, *sch_row = nullptr;
+  int32_t *segch_beg = nullptr, *segch_end = nullptr, *segch_row = nullptr;
   int32_t *ach_beg = nullptr, *ach_end = nullptr;
-  int32_t *fin_step_a0 = nullptr, *fin_step_a1 = nullptr, *fin_step_b0 = nullptr,
-          *fin_step_b1 = nullptr;
-  int32_t *fin_all_a0 = nullptr, *fin_all_a1 = nullptr, *fin_none = nullptr;
+  int32_t *seg_var = nullptr, *seg_q0 = nullptr, *seg_q1 = nullptr;
+  int32_t *heavy_var = nullptr, *heavy_sbeg = nullptr;
+  int32_t *fin_step_a0 = nullptr, *fin_step_a1 = nullptr;
+  int32_t *fin_all_a0 = nullptr, *fin_all_a1 = nullptr;
   // Empty clauses have no occurrence, so the step's variable pass never
   // sees them: the step's finalize adds n_empty.  Passes over every clause
   // (loss only, round check) count them themselves and add zero_empty.
@@ -108,6 +151,7 @@ struct galsat_ctx {
   // workspace
   float *D = nullptr, *xa = nullptr, *xb = nullptr;
   double* loss_part = nullptr;
+  double* gseg = nullptr;
   int32_t* unsat_part = nullptr;
   uint64_t* bits = nullptr;
   int32_t* best_tmp = nullptr;
@@ -249,6 +293,19 @@ const char* galsat_last_error(galsat_handle h) {
 
 namespace {
 
+// GALSAT_VERBOSE=1 prints the duration of each galsat_create phase.
+struct PhaseTimer {
+  bool on = std::getenv("GALSAT_VERBOSE") != nullptr;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    auto t1 = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[galsat] create %-18s %8.3f s\n", what,
+                 std::chrono::duration<double>(t1 - t0).count());
+    t0 = t1;
+  }
+};
+
 galsat_status create_fail(galsat_status s, const std::string& msg) {
   g_create_error = msg;
   return s;
@@ -315,35 +372,41 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   if (!(opt.lr >= 0.0f) || !std::isfinite(opt.lr)) return create_fail(GALSAT_EINVAL, "lr must be finite and >= 0");
 
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // ---- host copies of the inputs
-  std::vector<int32_t> cp((size_t)m + 1), cl((size_t)L), vp((size_t)n + 1), vo((size_t)L);
+  PhaseTimer ptimer;
+  // ---- host views of the inputs (copied only when they live on the device)
+  std::vector<int32_t> cp_own, cl_own, vp_own, vo_own;
+  const int32_t *cp = prob->clause_ptr, *cl = prob->clause_lits, *vp = prob->var_ptr,
+                *vo = prob->var_occ;
   std::vector<int32_t> fvb((size_t)F + 1), fcb((size_t)F + 1);
-  auto fetch = [&](std::vector<int32_t>& dst, const int32_t* src) -> hipError_t {
-    if (dst.empty()) return hipSuccess;
+  hipError_t he = hipSuccess;
+  auto fetch = [&](std::vector<int32_t>& dst, const int32_t* src, size_t count) -> hipError_t {
+    dst.resize(count);
+    if (count == 0) return hipSuccess;
     if (prob->inputs_on_device)
-      return hipMemcpy(dst.data(), src, dst.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
-    std::memcpy(dst.data(), src, dst.size() * sizeof(int32_t));
+      return hipMemcpy(dst.data(), src, count * sizeof(int32_t), hipMemcpyDeviceToHost);
+    std::memcpy(dst.data(), src, count * sizeof(int32_t));
     return hipSuccess;
   };
-  hipError_t he = hipSuccess;
-  if ((he = fetch(cp, prob->clause_ptr)) != hipSuccess || (he = fetch(vp, prob->var_ptr)) != hipSuccess ||
-      (L > 0 && (he = fetch(cl, prob->clause_lits)) != hipSuccess) ||
-      (L > 0 && (he = fetch(vo, prob->var_occ)) != hipSuccess))
-    return create_fail(GALSAT_EDEVICE, std::string("copying inputs: ") + hipGetErrorString(he));
-  if (F > 1) {
-    if ((he = fetch(fvb, prob->formula_var_begin)) != hipSuccess ||
-        (he = fetch(fcb, prob->formula_clause_begin)) != hipSuccess)
+  if (prob->inputs_on_device) {
+    if ((he = fetch(cp_own, prob->clause_ptr, (size_t)m + 1)) != hipSuccess ||
+        (he = fetch(vp_own, prob->var_ptr, (size_t)n + 1)) != hipSuccess ||
+        (he = fetch(cl_own, prob->clause_lits, (size_t)L)) != hipSuccess ||
+        (he = fetch(vo_own, prob->var_occ, (size_t)L)) != hipSuccess)
       return create_fail(GALSAT_EDEVICE, std::string("copying inputs: ") + hipGetErrorString(he));
+    cp = cp_own.data();
+    vp = vp_own.data();
+    cl = cl_own.data();
+    vo = vo_own.data();
+  }
+  if (prob->formula_var_begin && prob->formula_clause_begin) {
+    if ((he = fetch(fvb, prob->formula_var_begin, (size_t)F + 1)) != hipSuccess ||
+        (he = fetch(fcb, prob->formula_clause_begin, (size_t)F + 1)) != hipSuccess)
+      return create_fail(GALSAT_EDEVICE, std::string("copying formula ranges: ") + hipGetErrorString(he));
   } else {
     fvb = {0, n};
     fcb = {0, m};
-    if (prob->formula_var_begin) {
-      if ((he = fetch(fvb, prob->formula_var_begin)) != hipSuccess ||
-          (he = fetch(fcb, prob->formula_clause_begin ? prob->formula_clause_begin : nullptr)) != hipSuccess)
-        return create_fail(GALSAT_EDEVICE, "copying formula ranges");
-    }
   }
-
+  ptimer.mark("fetch");
   // ---- validation
   if (cp[0] != 0 || cp[(size_t)m] != L) return create_fail(GALSAT_EINVAL, "clause_ptr must start at 0 and end at n_lits");
   for (int32_t t = 0; t < m; ++t)
@@ -359,40 +422,70 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   std::vector<int32_t> var_formula((size_t)n);
   for (int32_t f = 0; f < F; ++f)
     for (int32_t v = fvb[f]; v < fvb[f + 1]; ++v) var_formula[v] = f;
-  std::vector<int32_t> clause_of((size_t)L);
-  int32_t kmax = 0;
-  std::vector<int32_t> n_empty((size_t)F, 0);
-  for (int32_t f = 0; f < F; ++f) {
-    for (int32_t t = fcb[f]; t < fcb[f + 1]; ++t) {
+  std::unique_ptr<int32_t[]> clause_of(new int32_t[(size_t)L + 1]);
+  std::atomic<int32_t> kmax_a{0};
+  std::vector<std::atomic<int32_t>> n_empty_a((size_t)F);
+  for (auto& e : n_empty_a) e.store(0);
+  FirstError ferr;
+  parallel_for(m, [&](int64_t t0, int64_t t1) {
+    if (t0 >= t1) return;
+    int32_t f = (int32_t)(std::upper_bound(fcb.begin(), fcb.end(), (int32_t)t0) - fcb.begin()) - 1;
+    int32_t kloc = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+      while (t >= fcb[f + 1]) ++f;
       const int32_t k = cp[t + 1] - cp[t];
-      kmax = std::max(kmax, k);
-      if (k == 0) n_empty[f]++;
+      kloc = std::max(kloc, k);
+      if (k == 0) n_empty_a[f]++;
       for (int32_t p = cp[t]; p < cp[t + 1]; ++p) {
         const int32_t code = cl[p];
-        if (code < 0 || (code >> 1) >= n)
-          return create_fail(GALSAT_EINVAL, "literal code out of range at position " + std::to_string(p));
-        if ((code >> 1) < fvb[f] || (code >> 1) >= fvb[f + 1])
-          return create_fail(GALSAT_EINVAL, "clause " + std::to_string(t) + " uses a variable of another formula");
-        clause_of[p] = t;
+        if (code < 0 || (code >> 1) >= n) {
+          ferr.report(p, "literal code out of range at position " + std::to_string(p));
+          return;
+        }
+        if ((code >> 1) < fvb[f] || (code >> 1) >= fvb[f + 1]) {
+          ferr.report(p, "clause " + std::to_string(t) + " uses a variable of another formula");
+          return;
+        }
+        clause_of[p] = (int32_t)t;
       }
     }
-  }
+    int32_t cur = kmax_a.load();
+    while (kloc > cur && !kmax_a.compare_exchange_weak(cur, kloc)) {
+    }
+  });
+  if (ferr.index >= 0) return create_fail(GALSAT_EINVAL, ferr.msg);
+  const int32_t kmax = kmax_a.load();
+  std::vector<int32_t> n_empty((size_t)F);
+  for (int32_t f = 0; f < F; ++f) n_empty[f] = n_empty_a[f].load();
   {
-    std::vector<uint8_t> seen(opt.validate ? (size_t)L : 0, 0);
-    for (int32_t v = 0; v < n; ++v)
-      for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
-        const int32_t p = vo[q];
-        if (p < 0 || p >= L) return create_fail(GALSAT_EINVAL, "var_occ entry out of range");
-        if ((cl[p] >> 1) != v)
-          return create_fail(GALSAT_EINVAL, "var_occ is not the transpose of clause_lits (variable " +
-                                                std::to_string(v) + ")");
-        if (opt.validate) {
-          if (seen[p]) return create_fail(GALSAT_EINVAL, "var_occ lists a position twice");
-          seen[p] = 1;
+    // every slot names a position of its own variable, each position once
+    std::unique_ptr<uint64_t[]> seen(opt.validate ? new uint64_t[(size_t)L / 64 + 1]() : nullptr);
+    parallel_for(n, [&](int64_t v0, int64_t v1) {
+      for (int64_t v = v0; v < v1; ++v)
+        for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
+          const int32_t p = vo[q];
+          if (p < 0 || p >= L) {
+            ferr.report(q, "var_occ entry out of range");
+            return;
+          }
+          if ((cl[p] >> 1) != v) {
+            ferr.report(q, "var_occ is not the transpose of clause_lits (variable " +
+                               std::to_string(v) + ")");
+            return;
+          }
+          if (seen) {
+            const uint64_t bit = 1ULL << (p & 63);
+            if (__atomic_fetch_or(&seen[p >> 6], bit, __ATOMIC_RELAXED) & bit) {
+              ferr.report(q, "var_occ lists a position twice");
+              return;
+            }
+          }
         }
-      }
+    });
+    if (ferr.index >= 0) return create_fail(GALSAT_EINVAL, ferr.msg);
   }
 
+  ptimer.mark("validate");
   std::unique_ptr<galsat_ctx> h(new galsat_ctx());
   h->F = F; h->n = n; h->m = m; h->L = L; h->R = R;
   h->opt = opt;
@@ -415,10 +508,14 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   h->ld = (int32_t)round_up(R, 4);
   h->ldD = round_up(R, 4);
   auto count_stored = [&](int32_t kr) {
-    int64_t c = 0;
-    for (int32_t t = 0; t < m; ++t)
-      if (cp[t + 1] - cp[t] > kr && cp[t + 1] > cp[t]) c += cp[t + 1] - cp[t];
-    return c;
+    std::atomic<int64_t> c{0};
+    parallel_for(m, [&](int64_t t0, int64_t t1) {
+      int64_t loc = 0;
+      for (int64_t t = t0; t < t1; ++t)
+        if (cp[t + 1] - cp[t] > kr && cp[t + 1] > cp[t]) loc += cp[t + 1] - cp[t];
+      c += loc;
+    });
+    return c.load();
   };
   int64_t stored = count_stored(krec);
   if (opt.workspace_budget_bytes > 0 &&
@@ -431,22 +528,56 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   h->krec = krec;
   h->stored = stored;
 
-  // occurrence records and stored-row numbering (var-major order)
-  std::vector<int32_t> occ_rec((size_t)L), lit_dslot(stored > 0 ? (size_t)L : 0, -1);
+  // Occurrence records in variable-major order (one int4 per slot; the
+  // kernels' record layout): stored partial row, a short recomputed clause
+  // with the other literals' codes inline, or a longer recomputed clause by
+  // id and position.  Stored rows are numbered in variable-major order so a
+  // variable's stored partials are contiguous.
+  // filled completely below, so left uninitialised
+  std::unique_ptr<int4[]> occ4(new int4[(size_t)L + 1]);
+  std::unique_ptr<int32_t[]> occ_cost(new int32_t[(size_t)L + 1]);
+  std::unique_ptr<int32_t[]> lit_dslot(new int32_t[stored > 0 ? (size_t)L + 1 : 1]);
   {
-    int64_t d = 0;
-    for (int32_t v = 0; v < n; ++v)
+    std::vector<int64_t> sbase((size_t)n + 1, 0);
+    parallel_for(n, [&](int64_t v0, int64_t v1) {
+      for (int64_t v = v0; v < v1; ++v) {
+        int64_t c = 0;
+        for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
+          const int32_t t = clause_of[vo[q]];
+          c += (cp[t + 1] - cp[t] > krec) ? 1 : 0;
+        }
+        sbase[v + 1] = c;
+      }
+    });
+    for (int32_t v = 0; v < n; ++v) sbase[v + 1] += sbase[v];
+    parallel_for(n, [&](int64_t v0, int64_t v1) {
+    for (int64_t vv = v0; vv < v1; ++vv) {
+      const int32_t v = (int32_t)vv;
+      int64_t d = sbase[v];
       for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
-        const int32_t p = vo[q], t = clause_of[p];
-        if (cp[t + 1] - cp[t] > krec) {
-          occ_rec[q] = -(int32_t)(d + 1);
+        const int32_t p = vo[q], t = clause_of[p], k = cp[t + 1] - cp[t];
+        if (k > krec) {
+          occ4[q] = make_int4(2 << 4, (int32_t)d, 0, 0);
+          occ_cost[q] = 1;
           lit_dslot[p] = (int32_t)d;
           ++d;
+        } else if (k <= 4) {
+          int32_t codes[3] = {2 * v, 2 * v, 2 * v};
+          int32_t c = 0;
+          for (int32_t i = cp[t]; i < cp[t + 1]; ++i)
+            if (i != p) codes[c++] = cl[i];
+          const int32_t hdr = (k - 1) | ((cl[p] & 1) << 2) | ((p == cp[t]) ? 8 : 0);
+          occ4[q] = make_int4(hdr, codes[0], codes[1], codes[2]);
+          occ_cost[q] = std::max(1, k - 1);
         } else {
-          occ_rec[q] = t;
+          occ4[q] = make_int4(1 << 4, t, p, 0);
+          occ_cost[q] = k - 1;
         }
       }
+    }
+    });
   }
+  ptimer.mark("records");
   std::vector<int32_t> stored_ids;
   std::vector<int64_t> f_sbeg((size_t)F + 1, 0);
   for (int32_t f = 0; f < F; ++f) {
@@ -456,20 +587,84 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   }
   f_sbeg[F] = (int64_t)stored_ids.size();
 
-  // ---- chunks of balanced cost
+  // ---- chunks of balanced cost.  The cost of a variable is its number of
+  // gathered rows per restart; a chunk (one workgroup) gets about
+  // total / chunks_target, and a variable costlier than one item slot's
+  // share (chunk target / items per workgroup) is split into segments whose
+  // partial gradients are summed in segment order by a second kernel.
   const int tiles = (R + h->tile.tile() - 1) / h->tile.tile();
   const int64_t chunks_target = std::max<int64_t>(1, kTargetBlocks / std::max(1, tiles));
+  const int ipb = kBlock / h->tile.lpi;
+  std::vector<int32_t> heavy, heavy_sbeg{0}, seg_var, seg_q0, seg_q1;
+  std::vector<int32_t> heavy_f_first((size_t)F + 1, 0);
   {
-    std::vector<int64_t> pre((size_t)n + 1, 0), fb(fvb.begin(), fvb.end());
-    for (int32_t v = 0; v < n; ++v) {
-      int64_t c = 1;
-      for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
-        const int32_t rec = occ_rec[q];
-        c += rec < 0 ? 1 : std::max(1, cp[rec + 1] - cp[rec] - 1);
+    std::vector<int64_t> vcost((size_t)n, 1);
+    parallel_for(n, [&](int64_t v0, int64_t v1) {
+      for (int64_t v = v0; v < v1; ++v)
+        for (int32_t q = vp[v]; q < vp[v + 1]; ++q) vcost[v] += occ_cost[q];
+    });
+    int64_t total = 0;
+    for (int32_t v = 0; v < n; ++v) total += vcost[v];
+    const int64_t target = std::max<int64_t>(64, total / chunks_target);
+    const int64_t item_cap = std::max<int64_t>(64, target / ipb);
+    Chunks vc, sc;
+    vc.f_first.assign((size_t)F + 1, 0);
+    sc.f_first.assign((size_t)F + 1, 0);
+    for (int32_t f = 0; f < F; ++f) {
+      vc.f_first[f] = vc.count();
+      heavy_f_first[f] = (int32_t)heavy.size();
+      int32_t cb = fvb[f];
+      int64_t acc = 0;
+      for (int32_t v = fvb[f]; v < fvb[f + 1]; ++v) {
+        if (vcost[v] > item_cap && vp[v + 1] - vp[v] > 1) {
+          if (v > cb) { vc.beg.push_back(cb); vc.end.push_back(v); }
+          cb = v + 1;
+          acc = 0;
+          heavy.push_back(v);
+          int64_t sacc = 0;
+          int32_t q0 = vp[v];
+          for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
+            sacc += occ_cost[q];
+            if (sacc >= item_cap || q + 1 == vp[v + 1]) {
+              seg_var.push_back(v);
+              seg_q0.push_back(q0);
+              seg_q1.push_back(q + 1);
+              q0 = q + 1;
+              sacc = 0;
+            }
+          }
+          heavy_sbeg.push_back((int32_t)seg_var.size());
+          continue;
+        }
+        acc += vcost[v];
+        if (acc >= target) {
+          vc.beg.push_back(cb);
+          vc.end.push_back(v + 1);
+          cb = v + 1;
+          acc = 0;
+        }
       }
-      pre[v + 1] = pre[v] + c;
+      if (fvb[f + 1] > cb) { vc.beg.push_back(cb); vc.end.push_back(fvb[f + 1]); }
+      // segment chunks of this formula: about `target` cost each
+      sc.f_first[f] = sc.count();
+      const int32_t s_lo = heavy_sbeg[heavy_f_first[f]], s_hi = (int32_t)seg_var.size();
+      int32_t sb = s_lo;
+      int64_t sacc = 0;
+      for (int32_t sg = s_lo; sg < s_hi; ++sg) {
+        for (int32_t q = seg_q0[sg]; q < seg_q1[sg]; ++q) sacc += occ_cost[q];
+        if (sacc >= target || sg + 1 == s_hi) {
+          sc.beg.push_back(sb);
+          sc.end.push_back(sg + 1);
+          sb = sg + 1;
+          sacc = 0;
+        }
+      }
     }
-    h->vch = make_chunks(F, fb, pre, std::max<int64_t>(64, pre[n] / chunks_target));
+    vc.f_first[F] = vc.count();
+    sc.f_first[F] = sc.count();
+    heavy_f_first[F] = (int32_t)heavy.size();
+    h->vch = vc;
+    h->segch = sc;
   }
   {
     std::vector<int64_t> pre(stored_ids.size() + 1, 0);
@@ -482,16 +677,28 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     for (int32_t t = 0; t < m; ++t) pre[t + 1] = pre[t] + 1 + (cp[t + 1] - cp[t]);
     h->ach = make_chunks(F, fb, pre, std::max<int64_t>(256, pre[m] / chunks_target));
   }
-  const int VC = h->vch.count(), SC = h->sch.count(), AC = h->ach.count();
-  std::vector<int32_t> fsa0(F), fsa1(F), fsb0(F), fsb1(F), faa0(F), faa1(F), fnone(F, 0);
-  for (int32_t f = 0; f < F; ++f) {
-    fsa0[f] = h->vch.f_first[f];
-    fsa1[f] = h->vch.f_first[f + 1];
-    fsb0[f] = VC + h->sch.f_first[f];
-    fsb1[f] = VC + h->sch.f_first[f + 1];
-    faa0[f] = h->ach.f_first[f];
-    faa1[f] = h->ach.f_first[f + 1];
+  ptimer.mark("chunks");
+  h->heavy_f_first = heavy_f_first;
+  h->n_heavy = (int32_t)heavy.size();
+  h->n_seg = (int32_t)seg_var.size();
+  // partial-sum rows of a step, contiguous per formula: its variable chunks,
+  // its stored-clause chunks, then its segment chunks
+  const int VC = h->vch.count(), SC = h->sch.count(), GC = h->segch.count(), AC = h->ach.count();
+  std::vector<int32_t> vrow(VC), srow(SC), grow(GC), frow0(F), frow1(F), faa0(F), faa1(F);
+  {
+    int32_t row = 0;
+    for (int32_t f = 0; f < F; ++f) {
+      frow0[f] = row;
+      for (int c = h->vch.f_first[f]; c < h->vch.f_first[f + 1]; ++c) vrow[c] = row++;
+      for (int c = h->sch.f_first[f]; c < h->sch.f_first[f + 1]; ++c) srow[c] = row++;
+      for (int c = h->segch.f_first[f]; c < h->segch.f_first[f + 1]; ++c) grow[c] = row++;
+      frow1[f] = row;
+      faa0[f] = h->ach.f_first[f];
+      faa1[f] = h->ach.f_first[f + 1];
+    }
+    h->step_rows = row;
   }
+  std::vector<int32_t> fnone(F, 0);
   // schedule
   h->schedule = opt.schedule == GALSAT_SCHED_PLAIN ? GALSAT_SCHED_PLAIN : GALSAT_SCHED_GENERAL;
 
@@ -509,27 +716,44 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,    \
                          std::string("allocate " #dst ": ") + hipGetErrorString(he));    \
   } while (0)
-  UP(clause_ptr, cp);
-  UP(clause_lits, cl);
-  UP(var_ptr, vp);
-  UP(var_occ, vo);
-  UP(occ_rec, occ_rec);
-  if (stored > 0) UP(lit_dslot, lit_dslot);
+#define UPP(dst, ptr, count)                                                             \
+  do {                                                                                   \
+    if ((he = c->upload(&c->dst, (ptr), (size_t)(count), s)) != hipSuccess)              \
+      return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,    \
+                         std::string("upload " #dst ": ") + hipGetErrorString(he));      \
+  } while (0)
+  UPP(clause_ptr, cp, m + 1);
+  UPP(clause_lits, cl, L);
+  UPP(var_ptr, vp, n + 1);
+#undef UPP
+  if ((he = c->upload(&c->occ4, occ4.get(), (size_t)L, s)) != hipSuccess)
+    return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
+                       std::string("upload occurrence records: ") + hipGetErrorString(he));
+  if (stored > 0 && (he = c->upload(&c->lit_dslot, lit_dslot.get(), (size_t)L, s)) != hipSuccess)
+    return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
+                       std::string("upload stored rows: ") + hipGetErrorString(he));
   UP(var_formula, var_formula);
   UP(stored_ids, stored_ids);
   UP(vch_beg, c->vch.beg);
   UP(vch_end, c->vch.end);
+  UP(vch_row, vrow);
   UP(sch_beg, c->sch.beg);
   UP(sch_end, c->sch.end);
+  UP(sch_row, srow);
+  UP(segch_beg, c->segch.beg);
+  UP(segch_end, c->segch.end);
+  UP(segch_row, grow);
   UP(ach_beg, c->ach.beg);
   UP(ach_end, c->ach.end);
-  UP(fin_step_a0, fsa0);
-  UP(fin_step_a1, fsa1);
-  UP(fin_step_b0, fsb0);
-  UP(fin_step_b1, fsb1);
+  UP(seg_var, seg_var);
+  UP(seg_q0, seg_q0);
+  UP(seg_q1, seg_q1);
+  UP(heavy_var, heavy);
+  UP(heavy_sbeg, heavy_sbeg);
+  UP(fin_step_a0, frow0);
+  UP(fin_step_a1, frow1);
   UP(fin_all_a0, faa0);
   UP(fin_all_a1, faa1);
-  UP(fin_none, fnone);
   UP(n_empty, n_empty);
   UP(zero_empty, fnone);
   UP(f_vbeg, fvb);
@@ -537,7 +761,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   if (stored > 0) AL(D, (size_t)stored * (size_t)c->ldD);
   AL(xa, (size_t)n * c->ld);
   AL(xb, (size_t)n * c->ld);
-  const int64_t rows = std::max<int64_t>(VC + SC, AC);
+  const int64_t rows = std::max<int64_t>(c->step_rows, AC);
+  AL(gseg, (size_t)std::max<int64_t>(c->n_seg, 1) * R);
   AL(loss_part, (size_t)std::max<int64_t>(rows, 1) * R);
   AL(unsat_part, (size_t)std::max<int64_t>(rows, 1) * R);
   AL(bits, (size_t)n * ((R + 63) / 64));
@@ -548,6 +773,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
 #undef AL
   if ((he = hipStreamSynchronize(s)) != hipSuccess)
     return create_fail(GALSAT_EDEVICE, std::string("create: ") + hipGetErrorString(he));
+  ptimer.mark("upload");
   *out = h.release();
   return GALSAT_OK;
 }
@@ -580,7 +806,7 @@ extern "C" galsat_status galsat_get_info(galsat_handle h, galsat_info* info) {
   info->schedule = h->schedule;
   info->lanes_per_item = h->tile.lpi;
   info->restarts_per_lane = h->tile.rpl;
-  info->var_chunks = h->vch.count();
+  info->var_chunks = h->vch.count() + h->segch.count();
   info->clause_chunks = h->sch.count();
   info->batched_items = 0;
   info->device_bytes = h->device_bytes;
@@ -616,12 +842,18 @@ Tile tile_for(const galsat_ctx* h, const void* a, int32_t lda, const void* b, in
 VarPassArgs var_args(const galsat_ctx* h) {
   VarPassArgs a{};
   a.var_ptr = h->var_ptr;
-  a.var_occ = h->var_occ;
-  a.occ_rec = h->occ_rec;
+  a.occ = h->occ4;
   a.clause_ptr = h->clause_ptr;
   a.clause_lits = h->clause_lits;
   a.chunk_vbeg = h->vch_beg;
   a.chunk_vend = h->vch_end;
+  a.chunk_row = h->vch_row;
+  a.seg_var = h->seg_var;
+  a.seg_q0 = h->seg_q0;
+  a.seg_q1 = h->seg_q1;
+  a.gseg = h->gseg;
+  a.heavy_var = h->heavy_var;
+  a.heavy_sbeg = h->heavy_sbeg;
   a.var_formula = h->var_formula;
   a.D = h->D;
   a.ldD = h->ldD;
@@ -635,21 +867,80 @@ VarPassArgs var_args(const galsat_ctx* h) {
   return a;
 }
 
-ClausePassArgs stored_clause_args(const galsat_ctx* h) {
-  ClausePassArgs a{};
-  a.clause_ptr = h->clause_ptr;
-  a.clause_lits = h->clause_lits;
-  a.lit_dslot = h->lit_dslot;
-  a.clause_ids = h->stored_ids;
-  a.chunk_cbeg = h->sch_beg;
-  a.chunk_cend = h->sch_end;
-  a.row_base = h->vch.count();
-  a.D = h->D;
-  a.ldD = h->ldD;
-  a.loss_part = h->loss_part;
-  a.unsat_part = h->unsat_part;
-  a.R = h->R;
-  return a;
+// Gradient passes for formulas [f0, f1) at state x: stored-clause partials,
+// whole variables, segments of split variables, then the split variables'
+// sums; every pass ends in the epilogue `mode` writing `out`.  The per-chunk
+// loss and unsat partial rows of the formulas are all written.
+galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32_t ldx,
+                          float* out, int32_t ldo, float* mom, float* vel, int32_t ldm,
+                          const float* upstream, int f0, int f1, hipStream_t s) {
+  VarPassArgs va = var_args(h);
+  va.x = x;
+  va.ldx = ldx;
+  va.out = out;
+  va.ldo = ldo;
+  va.mom = mom;
+  va.vel = vel;
+  va.ldm = ldm;
+  va.upstream = upstream;
+  if (mode == kModeAdam) {
+    const int tt = h->adam_t + 1;
+    va.inv_c1 = 1.0 / (1.0 - std::pow((double)h->opt.beta1, tt));
+    va.inv_c2 = 1.0 / (1.0 - std::pow((double)h->opt.beta2, tt));
+  }
+  const int sc0 = h->sch.f_first[f0], sc1 = h->sch.f_first[f1];
+  if (h->stored > 0 && sc1 > sc0) {
+    ClausePassArgs ca{};
+    ca.clause_ptr = h->clause_ptr;
+    ca.clause_lits = h->clause_lits;
+    ca.lit_dslot = h->lit_dslot;
+    ca.clause_ids = h->stored_ids;
+    ca.chunk_cbeg = h->sch_beg;
+    ca.chunk_cend = h->sch_end;
+    ca.chunk_row = h->sch_row;
+    ca.chunk_base = sc0;
+    ca.x = x;
+    ca.ldx = ldx;
+    ca.D = h->D;
+    ca.ldD = h->ldD;
+    ca.loss_part = h->loss_part;
+    ca.unsat_part = h->unsat_part;
+    ca.R = h->R;
+    ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
+    GS_HIP(h, launch_clause_pass(ca, true, t, sc1 - sc0, s), "clause pass");
+  }
+  const int vc0 = h->vch.f_first[f0], vc1 = h->vch.f_first[f1];
+  va.chunk_base = vc0;
+  {
+    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+    GS_HIP(h, launch_var_pass(va, mode, t, vc1 - vc0, s), "var pass");
+  }
+  const int gc0 = h->segch.f_first[f0], gc1 = h->segch.f_first[f1];
+  if (gc1 > gc0) {
+    VarPassArgs sa = va;
+    sa.chunk_vbeg = h->segch_beg;
+    sa.chunk_vend = h->segch_end;
+    sa.chunk_row = h->segch_row;
+    sa.chunk_base = gc0;
+    {
+      ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+      GS_HIP(h, launch_var_seg(sa, t, gc1 - gc0, s), "segment pass");
+    }
+    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+    GS_HIP(h, launch_heavy_finish(va, mode, t, h->heavy_f_first[f0], h->heavy_f_first[f1], s),
+           "split-variable finish");
+  }
+  return GALSAT_OK;
+}
+
+galsat_status finalize_step(galsat_ctx* h, float* loss, int32_t* unsat, int f0, int f1,
+                            hipStream_t s) {
+  if (!loss && !unsat) return GALSAT_OK;
+  FinalizeArgs fa{h->fin_step_a0, h->fin_step_a1, h->n_empty, h->loss_part, h->unsat_part,
+                  loss, unsat, h->R, f0};
+  ProfScope _ps(h, GALSAT_K_FINALIZE, s);
+  GS_HIP(h, launch_finalize(fa, f1 - f0, s), "finalize");
+  return GALSAT_OK;
 }
 
 }  // namespace
@@ -671,7 +962,7 @@ extern "C" galsat_status galsat_loss_grad(galsat_handle h, const float* x, int32
     a.clause_ids = nullptr;
     a.chunk_cbeg = h->ach_beg;
     a.chunk_cend = h->ach_end;
-    a.row_base = 0;
+    a.chunk_row = nullptr;
     a.x = x;
     a.ldx = ldx;
     a.loss_part = h->loss_part;
@@ -681,91 +972,30 @@ extern "C" galsat_status galsat_loss_grad(galsat_handle h, const float* x, int32
       ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
       GS_HIP(h, launch_clause_pass(a, false, t, h->ach.count(), s), "clause pass");
     }
-    FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->fin_none, h->fin_none, h->zero_empty,
-                    h->loss_part, h->unsat_part, loss, nullptr, h->R, 0};
-    {
-      ProfScope _ps(h, GALSAT_K_FINALIZE, s);
-      GS_HIP(h, launch_finalize(fa, F, s), "finalize");
-    }
+    FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->zero_empty, h->loss_part, h->unsat_part,
+                    loss, nullptr, h->R, 0};
+    ProfScope _ps(h, GALSAT_K_FINALIZE, s);
+    GS_HIP(h, launch_finalize(fa, F, s), "finalize");
     return GALSAT_OK;
   }
   Tile t = tile_for(h, x, ldx, grad, ldx);
-  if (h->stored > 0) {
-    ClausePassArgs ca = stored_clause_args(h);
-    ca.x = x;
-    ca.ldx = ldx;
-    {
-      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
-      GS_HIP(h, launch_clause_pass(ca, true, t, h->sch.count(), s), "clause pass");
-    }
-  }
-  VarPassArgs va = var_args(h);
-  va.x = x;
-  va.ldx = ldx;
-  va.out = grad;
-  va.ldo = ldx;
-  va.upstream = upstream;
-  {
-    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
-    GS_HIP(h, launch_var_pass(va, kModeGrad, t, h->vch.count(), s), "var pass");
-  }
-  FinalizeArgs fa{h->fin_step_a0, h->fin_step_a1, h->fin_step_b0, h->fin_step_b1, h->n_empty,
-                  h->loss_part, h->unsat_part, loss, nullptr, h->R, 0};
-  {
-    ProfScope _ps(h, GALSAT_K_FINALIZE, s);
-    GS_HIP(h, launch_finalize(fa, F, s), "finalize");
-  }
-  return GALSAT_OK;
+  galsat_status st = grad_passes(h, t, kModeGrad, x, ldx, grad, ldx, nullptr, nullptr, 0,
+                                 upstream, 0, F, s);
+  if (st != GALSAT_OK) return st;
+  return finalize_step(h, loss, nullptr, 0, F, s);
 }
 
 namespace {
 
-// One general-schedule step from xin to xout (internal layout, ld).
+// One step from xin to xout (internal layout) for formulas [f0, f1).
 galsat_status general_step(galsat_ctx* h, Tile t, const float* xin, float* xout, float* mom,
                            float* vel, int32_t ldm, float* loss_row, int32_t* unsat_row,
-                           hipStream_t s, int f_only) {
+                           hipStream_t s, int f0, int f1) {
   const int mode = h->opt.optimizer == GALSAT_OPT_ADAM ? kModeAdam : kModeSGD;
-  VarPassArgs va = var_args(h);
-  va.x = xin;
-  va.ldx = h->ld;
-  va.out = xout;
-  va.ldo = h->ld;
-  va.mom = mom;
-  va.vel = vel;
-  va.ldm = ldm;
-  if (mode == kModeAdam) {
-    const int tt = h->adam_t + 1;
-    va.inv_c1 = 1.0 / (1.0 - std::pow((double)h->opt.beta1, tt));
-    va.inv_c2 = 1.0 / (1.0 - std::pow((double)h->opt.beta2, tt));
-  }
-  ClausePassArgs ca = stored_clause_args(h);
-  ca.x = xin;
-  ca.ldx = h->ld;
-  int f0 = 0, f1 = h->F;
-  if (f_only >= 0) { f0 = f_only; f1 = f_only + 1; }
-  const int vc0 = h->vch.f_first[f0], vc1 = h->vch.f_first[f1];
-  const int sc0 = h->sch.f_first[f0], sc1 = h->sch.f_first[f1];
-  if (h->stored > 0 && sc1 > sc0) {
-    ca.chunk_base = sc0;
-    {
-      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
-      GS_HIP(h, launch_clause_pass(ca, true, t, sc1 - sc0, s), "clause pass");
-    }
-  }
-  va.chunk_base = vc0;
-  {
-    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
-    GS_HIP(h, launch_var_pass(va, mode, t, vc1 - vc0, s), "var pass");
-  }
-  if (loss_row || unsat_row) {
-    FinalizeArgs fa{h->fin_step_a0, h->fin_step_a1, h->fin_step_b0, h->fin_step_b1, h->n_empty,
-                    h->loss_part, h->unsat_part, loss_row, unsat_row, h->R, f0};
-    {
-      ProfScope _ps(h, GALSAT_K_FINALIZE, s);
-      GS_HIP(h, launch_finalize(fa, f1 - f0, s), "finalize");
-    }
-  }
-  return GALSAT_OK;
+  galsat_status st = grad_passes(h, t, mode, xin, h->ld, xout, h->ld, mom, vel, ldm, nullptr,
+                                 f0, f1, s);
+  if (st != GALSAT_OK) return st;
+  return finalize_step(h, loss_row, unsat_row, f0, f1, s);
 }
 
 }  // namespace
@@ -798,11 +1028,11 @@ extern "C" galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, flo
     int32_t* urow = unsat_trace ? unsat_trace + k * FR : nullptr;
     if (h->schedule == GALSAT_SCHED_PLAIN) {
       for (int f = 0; f < h->F; ++f) {
-        galsat_status st = general_step(h, t, cur, nxt, mom, vel, ldx, lrow, urow, s, f);
+        galsat_status st = general_step(h, t, cur, nxt, mom, vel, ldx, lrow, urow, s, f, f + 1);
         if (st != GALSAT_OK) return st;
       }
     } else {
-      galsat_status st = general_step(h, t, cur, nxt, mom, vel, ldx, lrow, urow, s, -1);
+      galsat_status st = general_step(h, t, cur, nxt, mom, vel, ldx, lrow, urow, s, 0, h->F);
       if (st != GALSAT_OK) return st;
     }
     if (adam) h->adam_t++;
@@ -832,8 +1062,8 @@ extern "C" galsat_status galsat_round_check(galsat_handle h, const float* x, int
                                  h->bits, h->n, h->R, h->unsat_part, s),
            "count unsat");
   }
-  FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->fin_none, h->fin_none, h->zero_empty,
-                  h->loss_part, h->unsat_part, nullptr, unsat, h->R, 0};
+  FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->zero_empty, h->loss_part, h->unsat_part,
+                  nullptr, unsat, h->R, 0};
   {
     ProfScope _ps(h, GALSAT_K_FINALIZE, s);
     GS_HIP(h, launch_finalize(fa, h->F, s), "finalize");

@@ -26,12 +26,18 @@ struct Tile {
 // Arguments of the variable-parallel pass (backward gather + fused update).
 struct VarPassArgs {
   const int32_t* var_ptr;
-  const int32_t* var_occ;
-  const int32_t* occ_rec;       // >= 0: clause id to recompute; < 0: -(stored row + 1)
+  const int4* occ;              // [L] occurrence record of each variable-major slot
   const int32_t* clause_ptr;
   const int32_t* clause_lits;
-  const int32_t* chunk_vbeg;    // [chunks] variable range of each chunk
+  const int32_t* chunk_vbeg;    // [chunks] item range of each chunk (variables or segments)
   const int32_t* chunk_vend;
+  const int32_t* chunk_row;     // [chunks] partial-sum row of each chunk
+  const int32_t* seg_var;       // [segments] variable of each segment of a split variable
+  const int32_t* seg_q0;        // [segments] occurrence range of the segment
+  const int32_t* seg_q1;
+  double* gseg;                 // [segments][R] partial gradients of the segments
+  const int32_t* heavy_var;     // [heavy] split variables
+  const int32_t* heavy_sbeg;    // [heavy+1] segment range of each split variable
   const int32_t* var_formula;   // [n] formula of each variable (upstream scaling)
   int32_t chunk_base;           // first chunk of this launch
   const float* x;
@@ -61,8 +67,8 @@ struct ClausePassArgs {
   const int32_t* clause_ids;    // [list] clause ids, or null for identity
   const int32_t* chunk_cbeg;    // [chunks] range in the clause list
   const int32_t* chunk_cend;
+  const int32_t* chunk_row;     // [chunks] partial-sum row, or null for row = chunk
   int32_t chunk_base;
-  int32_t row_base;             // partial row of chunk 0
   const float* x;
   int32_t ldx;
   float* D;
@@ -73,10 +79,8 @@ struct ClausePassArgs {
 };
 
 struct FinalizeArgs {
-  const int32_t* a_beg;         // [F] partial rows [a_beg, a_end) and [b_beg, b_end)
+  const int32_t* a_beg;         // [F] partial rows [a_beg, a_end) of each formula
   const int32_t* a_end;
-  const int32_t* b_beg;
-  const int32_t* b_end;
   const int32_t* n_empty;       // [F] empty clauses (U = 1, always unsatisfied)
   const double* loss_part;
   const int32_t* unsat_part;
@@ -90,6 +94,9 @@ enum VarMode { kModeSGD = 0, kModeAdam = 1, kModeGrad = 2 };
 
 // Launchers (galsat_kernels.hip).  All return the launch's hipError_t.
 hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s);
+hipError_t launch_var_seg(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
+hipError_t launch_heavy_finish(const VarPassArgs& a, int mode, Tile t, int h0, int h1,
+                               hipStream_t s);
 hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int chunks,
                               hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, int F, hipStream_t s);

@@ -104,16 +104,211 @@ __device__ __forceinline__ void block_partials(const double (&lsum)[RPL], const 
 
 // ------------------------------------------------------- variable pass
 //
-// For each variable v of the chunk and each restart r of the lane:
+// For a variable v and the restarts r of the lane, the gradient is
 //   g[v][r] = sum over the occurrences q of v (var_occ order) of
 //             dU_t/dx_v = slope_j * prod_{i != j} factor_i,
-// taking the product over the other literals either from the stored
-// partial row (occ_rec < 0) or by recomputing it from x (occ_rec = t).
-// The occurrence that is the first literal of a recomputed clause also
+// with the product over the other literals taken either from the stored
+// partial row or recomputed from x.  The
+// occurrence that is the first literal of a recomputed clause also
 // accounts for that clause's U_t and its rounded satisfaction, so each
-// clause enters the loss and the unsat count exactly once.  The epilogue
-// applies the projected SGD or Adam update (writing the next state) or
-// writes the (upstream-scaled) gradient.
+// clause enters the loss and the unsat count exactly once.
+
+// Occurrence records (one int4 per variable-major slot, see the host's
+// plan): x = header, y/z/w = payload.
+//   SHORT   recomputed clause of at most 4 literals: header bits 0-1 hold the
+//           number of other literals (0..3), bit 2 the own literal's sign
+//           (1 = negated), bit 3 whether the own literal is the clause's
+//           first; y, z, w the other literals' codes (unused ones repeat
+//           the own variable, so every load stays in bounds).
+//   GENERAL recomputed longer clause: y = clause id, z = own position.
+//   STORED  partial stored by the clause pass: y = stored row.
+constexpr int kRecShort = 0, kRecStored = 2;  // kind 1 is GENERAL
+__device__ __forceinline__ int rec_kind(int hdr) { return hdr >> 4; }
+
+// Contribution of one occurrence whose other-literal product is prod: the
+// slope of the own factor times prod, and, for the clause's first literal,
+// the clause's U and rounded satisfaction.
+template <int RPL>
+__device__ __forceinline__ void add_occurrence(bool own_neg, bool first, const float (&prod)[RPL],
+                                               const bool (&any_true)[RPL], const float (&xv)[RPL],
+                                               double (&g)[RPL], double (&lsum)[RPL],
+                                               int (&usum)[RPL]) {
+  const int own = own_neg ? 1 : 0;
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) g[j] += (double)(own_neg ? prod[j] : -prod[j]);
+  if (first) {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      lsum[j] += (double)(lit_factor(own, xv[j]) * prod[j]);
+      usum[j] += (any_true[j] || lit_true(own, xv[j])) ? 0 : 1;
+    }
+  }
+}
+
+// Four consecutive SHORT occurrences: all row gathers are issued before any
+// product is formed, so a wave keeps up to twelve loads in flight.
+template <int RPL>
+__device__ __forceinline__ void short4(const VarPassArgs& a, const int4 (&o)[4], int r0,
+                                       const float (&xv)[RPL], double (&g)[RPL],
+                                       double (&lsum)[RPL], int (&usum)[RPL]) {
+  float y[4][3][RPL];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    load_row<RPL>(a.x + (int64_t)(o[k].y >> 1) * a.ldx + r0, y[k][0]);
+    load_row<RPL>(a.x + (int64_t)(o[k].z >> 1) * a.ldx + r0, y[k][1]);
+    load_row<RPL>(a.x + (int64_t)(o[k].w >> 1) * a.ldx + r0, y[k][2]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int hdr = o[k].x, nother = hdr & 3;
+    const int codes[3] = {o[k].y, o[k].z, o[k].w};
+    float prod[RPL];
+    bool any_true[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      prod[j] = 1.0f;
+      any_true[j] = false;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool use = c < nother;
+        prod[j] *= use ? lit_factor(codes[c], y[k][c][j]) : 1.0f;
+        any_true[j] = any_true[j] || (use && lit_true(codes[c], y[k][c][j]));
+      }
+    }
+    add_occurrence<RPL>((hdr & 4) != 0, (hdr & 8) != 0, prod, any_true, xv, g, lsum, usum);
+  }
+}
+
+// One occurrence of any kind.
+template <int RPL>
+__device__ __forceinline__ void one_occurrence(const VarPassArgs& a, const int4 o, int r0,
+                                               const float (&xv)[RPL], double (&g)[RPL],
+                                               double (&lsum)[RPL], int (&usum)[RPL]) {
+  const int kind = rec_kind(o.x);
+  if (kind == kRecStored) {
+    float d[RPL];
+    load_row<RPL>(a.D + (int64_t)o.y * a.ldD + r0, d);
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) g[j] += (double)d[j];
+    return;
+  }
+  float prod[RPL];
+  bool any_true[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) { prod[j] = 1.0f; any_true[j] = false; }
+  bool own_neg, first;
+  if (kind == kRecShort) {
+    const int nother = o.x & 3;
+    const int codes[3] = {o.y, o.z, o.w};
+    for (int c = 0; c < nother; ++c) {
+      float y[RPL];
+      load_row<RPL>(a.x + (int64_t)(codes[c] >> 1) * a.ldx + r0, y);
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        prod[j] *= lit_factor(codes[c], y[j]);
+        any_true[j] = any_true[j] || lit_true(codes[c], y[j]);
+      }
+    }
+    own_neg = (o.x & 4) != 0;
+    first = (o.x & 8) != 0;
+  } else {
+    const int t = o.y, p = o.z;
+    const int cs = a.clause_ptr[t], ce = a.clause_ptr[t + 1];
+    for (int i = cs; i < ce; ++i) {
+      if (i == p) continue;
+      const int code = a.clause_lits[i];
+      float y[RPL];
+      load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + r0, y);
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        prod[j] *= lit_factor(code, y[j]);
+        any_true[j] = any_true[j] || lit_true(code, y[j]);
+      }
+    }
+    own_neg = (a.clause_lits[p] & 1) != 0;
+    first = p == cs;
+  }
+  add_occurrence<RPL>(own_neg, first, prod, any_true, xv, g, lsum, usum);
+}
+
+// Adds the contributions of occurrences [q0, q1) (in that order) of the
+// variable whose own state is xv.  Inactive lanes (restarts >= R) skip all
+// row traffic.
+template <int RPL>
+__device__ __forceinline__ void gather_occurrences(const VarPassArgs& a, int q0, int q1,
+                                                   bool active, int r0, const float (&xv)[RPL],
+                                                   double (&g)[RPL], double (&lsum)[RPL],
+                                                   int (&usum)[RPL]) {
+  if (!active) return;
+  int q = q0;
+  while (q < q1) {
+    if (q + 4 <= q1) {
+      const int4 o[4] = {a.occ[q], a.occ[q + 1], a.occ[q + 2], a.occ[q + 3]};
+      const int kinds = rec_kind(o[0].x) | rec_kind(o[1].x) | rec_kind(o[2].x) | rec_kind(o[3].x);
+      if (kinds == kRecShort) {
+        short4<RPL>(a, o, r0, xv, g, lsum, usum);
+        q += 4;
+        continue;
+      }
+      if (rec_kind(o[0].x) == kRecStored && rec_kind(o[1].x) == kRecStored &&
+          rec_kind(o[2].x) == kRecStored && rec_kind(o[3].x) == kRecStored) {
+        float d[4][RPL];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) load_row<RPL>(a.D + (int64_t)o[k].y * a.ldD + r0, d[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) g[j] += (double)d[k][j];
+        q += 4;
+        continue;
+      }
+    }
+    one_occurrence<RPL>(a, a.occ[q], r0, xv, g, lsum, usum);
+    ++q;
+  }
+}
+
+// The epilogue for one variable row: projected SGD or Adam update (writing
+// the next state) or the (upstream-scaled) gradient.
+template <int RPL, int MODE>
+__device__ __forceinline__ void var_epilogue(const VarPassArgs& a, int v, int r0,
+                                             const float (&xv)[RPL], const double (&g)[RPL]) {
+  float o[RPL];
+  if constexpr (MODE == kModeSGD) {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) o[j] = clamp01((double)xv[j] - (double)a.lr * g[j]);
+  } else if constexpr (MODE == kModeAdam) {
+    float m[RPL], s2[RPL];
+    float* mp = a.mom + (int64_t)v * a.ldm + r0;
+    float* vp = a.vel + (int64_t)v * a.ldm + r0;
+    load_row<RPL>(mp, m);
+    load_row<RPL>(vp, s2);
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      const double mm = (double)a.b1 * (double)m[j] + (1.0 - (double)a.b1) * g[j];
+      const double vv = (double)a.b2 * (double)s2[j] + (1.0 - (double)a.b2) * g[j] * g[j];
+      m[j] = (float)mm;
+      s2[j] = (float)vv;
+      const double step = (double)a.lr * ((double)m[j] * a.inv_c1) /
+                          (sqrt((double)s2[j] * a.inv_c2) + (double)a.eps);
+      o[j] = clamp01((double)xv[j] - step);
+    }
+    store_row<RPL>(mp, m);
+    store_row<RPL>(vp, s2);
+  } else {
+    const int R = a.R;
+    const int f = a.upstream ? a.var_formula[v] : 0;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      const double w = a.upstream ? (double)a.upstream[(int64_t)f * R + r0 + j] : 1.0;
+      o[j] = (float)(w * g[j]);
+    }
+  }
+  store_row<RPL>(a.out + (int64_t)v * a.ldo + r0, o);
+}
+
+// Variables of the chunk's range (the ranges exclude split variables): the
+// whole gradient, then the epilogue.
 template <int LPI, int RPL, int MODE>
 __global__ __launch_bounds__(kBlock) void k_var_pass(VarPassArgs a) {
   constexpr int IPB = kBlock / LPI;
@@ -135,84 +330,68 @@ __global__ __launch_bounds__(kBlock) void k_var_pass(VarPassArgs a) {
 #pragma unroll
     for (int j = 0; j < RPL; ++j) { g[j] = 0.0; xv[j] = 0.0f; }
     if (active) load_row<RPL>(a.x + (int64_t)v * a.ldx + r0, xv);
-    const int qb = a.var_ptr[v], qe = a.var_ptr[v + 1];
-    for (int q = qb; q < qe; ++q) {
-      const int rec = a.occ_rec[q];
-      if (rec < 0) {
-        if (active) {
-          float d[RPL];
-          load_row<RPL>(a.D + (int64_t)(-rec - 1) * a.ldD + r0, d);
-#pragma unroll
-          for (int j = 0; j < RPL; ++j) g[j] += (double)d[j];
-        }
-        continue;
-      }
-      const int p = a.var_occ[q];
-      const int cs = a.clause_ptr[rec], ce = a.clause_ptr[rec + 1];
-      float prod[RPL];
-      bool any_true[RPL];
-#pragma unroll
-      for (int j = 0; j < RPL; ++j) { prod[j] = 1.0f; any_true[j] = false; }
-      for (int i = cs; i < ce; ++i) {
-        if (i == p) continue;
-        const int code = a.clause_lits[i];
-        if (active) {
-          float y[RPL];
-          load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + r0, y);
-#pragma unroll
-          for (int j = 0; j < RPL; ++j) {
-            prod[j] *= lit_factor(code, y[j]);
-            any_true[j] = any_true[j] || lit_true(code, y[j]);
-          }
-        }
-      }
-      const int own = a.clause_lits[p];
-      const float slope = (own & 1) ? 1.0f : -1.0f;
-#pragma unroll
-      for (int j = 0; j < RPL; ++j) g[j] += (double)(slope * prod[j]);
-      if (p == cs) {
-#pragma unroll
-        for (int j = 0; j < RPL; ++j) {
-          lsum[j] += (double)(lit_factor(own, xv[j]) * prod[j]);
-          usum[j] += (any_true[j] || lit_true(own, xv[j])) ? 0 : 1;
-        }
-      }
-    }
-    if (!active) continue;
-    float o[RPL];
-    if constexpr (MODE == kModeSGD) {
-#pragma unroll
-      for (int j = 0; j < RPL; ++j) o[j] = clamp01((double)xv[j] - (double)a.lr * g[j]);
-    } else if constexpr (MODE == kModeAdam) {
-      float m[RPL], s2[RPL];
-      float* mp = a.mom + (int64_t)v * a.ldm + r0;
-      float* vp = a.vel + (int64_t)v * a.ldm + r0;
-      load_row<RPL>(mp, m);
-      load_row<RPL>(vp, s2);
-#pragma unroll
-      for (int j = 0; j < RPL; ++j) {
-        const double mm = (double)a.b1 * (double)m[j] + (1.0 - (double)a.b1) * g[j];
-        const double vv = (double)a.b2 * (double)s2[j] + (1.0 - (double)a.b2) * g[j] * g[j];
-        m[j] = (float)mm;
-        s2[j] = (float)vv;
-        const double step = (double)a.lr * ((double)m[j] * a.inv_c1) /
-                            (sqrt((double)s2[j] * a.inv_c2) + (double)a.eps);
-        o[j] = clamp01((double)xv[j] - step);
-      }
-      store_row<RPL>(mp, m);
-      store_row<RPL>(vp, s2);
-    } else {
-      const int R = a.R;
-      const int f = a.upstream ? a.var_formula[v] : 0;
-#pragma unroll
-      for (int j = 0; j < RPL; ++j) {
-        const double w = a.upstream ? (double)a.upstream[(int64_t)f * R + r0 + j] : 1.0;
-        o[j] = (float)(w * g[j]);
-      }
-    }
-    store_row<RPL>(a.out + (int64_t)v * a.ldo + r0, o);
+    gather_occurrences<RPL>(a, a.var_ptr[v], a.var_ptr[v + 1], active, r0, xv, g, lsum, usum);
+    if (active) var_epilogue<RPL, MODE>(a, v, r0, xv, g);
   }
-  block_partials<LPI, RPL>(lsum, usum, chunk, a.R, a.loss_part, a.unsat_part);
+  block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], a.R, a.loss_part, a.unsat_part);
+}
+
+// Segments of split variables (variables with more occurrences than one
+// item should serialise): each segment's partial gradient goes to
+// gseg[s][r] in FP64.
+template <int LPI, int RPL>
+__global__ __launch_bounds__(kBlock) void k_var_seg(VarPassArgs a) {
+  constexpr int IPB = kBlock / LPI;
+  constexpr int RT = LPI * RPL;
+  const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
+  const int chunk = a.chunk_base + blockIdx.x;
+  const int r0 = blockIdx.y * RT + lane * RPL;
+  const bool active = r0 < a.R;
+  const int sb = a.chunk_vbeg[chunk], se = a.chunk_vend[chunk];
+  double lsum[RPL];
+  int usum[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) { lsum[j] = 0.0; usum[j] = 0; }
+
+  for (int s0 = sb + slot; s0 < se; s0 += IPB) {
+    const int sgi = uniform<LPI>(s0);
+    const int v = a.seg_var[sgi];
+    double g[RPL];
+    float xv[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) { g[j] = 0.0; xv[j] = 0.0f; }
+    if (active) load_row<RPL>(a.x + (int64_t)v * a.ldx + r0, xv);
+    gather_occurrences<RPL>(a, a.seg_q0[sgi], a.seg_q1[sgi], active, r0, xv, g, lsum, usum);
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) a.gseg[(int64_t)sgi * a.R + r0 + j] = g[j];
+    }
+  }
+  block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], a.R, a.loss_part, a.unsat_part);
+}
+
+// Split variables: their segments' partial gradients summed in segment
+// order, then the same epilogue as k_var_pass.
+template <int LPI, int RPL, int MODE>
+__global__ __launch_bounds__(kBlock) void k_heavy_finish(VarPassArgs a, int h0, int h1) {
+  constexpr int IPB = kBlock / LPI;
+  constexpr int RT = LPI * RPL;
+  const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
+  const int r0 = blockIdx.y * RT + lane * RPL;
+  if (r0 >= a.R) return;
+  for (int i = h0 + blockIdx.x * IPB + slot; i < h1; i += gridDim.x * IPB) {
+    const int v = a.heavy_var[i];
+    double g[RPL];
+    float xv[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) g[j] = 0.0;
+    load_row<RPL>(a.x + (int64_t)v * a.ldx + r0, xv);
+    for (int sgi = a.heavy_sbeg[i]; sgi < a.heavy_sbeg[i + 1]; ++sgi) {
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) g[j] += a.gseg[(int64_t)sgi * a.R + r0 + j];
+    }
+    var_epilogue<RPL, MODE>(a, v, r0, xv, g);
+  }
 }
 
 // -------------------------------------------------------- clause pass
@@ -282,8 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_clause_pass(ClausePassArgs a) {
       }
     }
   }
-  block_partials<LPI, RPL>(lsum, usum, (int64_t)a.row_base + chunk, a.R, a.loss_part,
-                           a.unsat_part);
+  block_partials<LPI, RPL>(lsum, usum, a.chunk_row ? a.chunk_row[chunk] : chunk, a.R,
+                           a.loss_part, a.unsat_part);
 }
 
 // ------------------------------------------------------------ finalize
@@ -299,10 +478,6 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a) {
   int uacc = 0;
   if (r < R) {
     for (int row = a.a_beg[f] + w; row < a.a_end[f]; row += 4) {
-      if (a.loss_out) acc += a.loss_part[(int64_t)row * R + r];
-      if (a.unsat_out) uacc += a.unsat_part[(int64_t)row * R + r];
-    }
-    for (int row = a.b_beg[f] + w; row < a.b_end[f]; row += 4) {
       if (a.loss_out) acc += a.loss_part[(int64_t)row * R + r];
       if (a.unsat_out) uacc += a.unsat_part[(int64_t)row * R + r];
     }
@@ -466,6 +641,44 @@ hipError_t var_pass_lpi(const VarPassArgs& a, int mode, Tile t, int chunks, int 
 }
 
 template <int LPI, int RPL>
+hipError_t var_seg_rpl(const VarPassArgs& a, int chunks, int tiles, hipStream_t s) {
+  hipLaunchKernelGGL((k_var_seg<LPI, RPL>), dim3(chunks, tiles), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int LPI>
+hipError_t var_seg_lpi(const VarPassArgs& a, Tile t, int chunks, int tiles, hipStream_t s) {
+  switch (t.rpl) {
+    case 4: return var_seg_rpl<LPI, 4>(a, chunks, tiles, s);
+    case 2: return var_seg_rpl<LPI, 2>(a, chunks, tiles, s);
+    default: return var_seg_rpl<LPI, 1>(a, chunks, tiles, s);
+  }
+}
+
+template <int LPI, int RPL>
+hipError_t heavy_rpl(const VarPassArgs& a, int mode, int h0, int h1, int tiles, hipStream_t s) {
+  constexpr int IPB = kBlock / LPI;
+  int blocks = (h1 - h0 + IPB - 1) / IPB;
+  blocks = blocks > 4096 ? 4096 : blocks;
+  dim3 grid(blocks, tiles), block(kBlock);
+  switch (mode) {
+    case kModeSGD: hipLaunchKernelGGL((k_heavy_finish<LPI, RPL, kModeSGD>), grid, block, 0, s, a, h0, h1); break;
+    case kModeAdam: hipLaunchKernelGGL((k_heavy_finish<LPI, RPL, kModeAdam>), grid, block, 0, s, a, h0, h1); break;
+    default: hipLaunchKernelGGL((k_heavy_finish<LPI, RPL, kModeGrad>), grid, block, 0, s, a, h0, h1); break;
+  }
+  return hipGetLastError();
+}
+
+template <int LPI>
+hipError_t heavy_lpi(const VarPassArgs& a, int mode, Tile t, int h0, int h1, int tiles, hipStream_t s) {
+  switch (t.rpl) {
+    case 4: return heavy_rpl<LPI, 4>(a, mode, h0, h1, tiles, s);
+    case 2: return heavy_rpl<LPI, 2>(a, mode, h0, h1, tiles, s);
+    default: return heavy_rpl<LPI, 1>(a, mode, h0, h1, tiles, s);
+  }
+}
+
+template <int LPI, int RPL>
 hipError_t clause_pass_rpl(const ClausePassArgs& a, bool write_d, int chunks, int tiles, hipStream_t s) {
   dim3 grid(chunks, tiles), block(kBlock);
   if (write_d) hipLaunchKernelGGL((k_clause_pass<LPI, RPL, true>), grid, block, 0, s, a);
@@ -499,6 +712,31 @@ hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, h
     case 16: return var_pass_lpi<16>(a, mode, t, chunks, tiles, s);
     case 32: return var_pass_lpi<32>(a, mode, t, chunks, tiles, s);
     default: return var_pass_lpi<64>(a, mode, t, chunks, tiles, s);
+  }
+}
+
+hipError_t launch_var_seg(const VarPassArgs& a, Tile t, int chunks, hipStream_t s) {
+  if (chunks <= 0) return hipSuccess;
+  const int tiles = (a.R + t.tile() - 1) / t.tile();
+  switch (t.lpi) {
+    case 4: return var_seg_lpi<4>(a, t, chunks, tiles, s);
+    case 8: return var_seg_lpi<8>(a, t, chunks, tiles, s);
+    case 16: return var_seg_lpi<16>(a, t, chunks, tiles, s);
+    case 32: return var_seg_lpi<32>(a, t, chunks, tiles, s);
+    default: return var_seg_lpi<64>(a, t, chunks, tiles, s);
+  }
+}
+
+hipError_t launch_heavy_finish(const VarPassArgs& a, int mode, Tile t, int h0, int h1,
+                               hipStream_t s) {
+  if (h1 <= h0) return hipSuccess;
+  const int tiles = (a.R + t.tile() - 1) / t.tile();
+  switch (t.lpi) {
+    case 4: return heavy_lpi<4>(a, mode, t, h0, h1, tiles, s);
+    case 8: return heavy_lpi<8>(a, mode, t, h0, h1, tiles, s);
+    case 16: return heavy_lpi<16>(a, mode, t, h0, h1, tiles, s);
+    case 32: return heavy_lpi<32>(a, mode, t, h0, h1, tiles, s);
+    default: return heavy_lpi<64>(a, mode, t, h0, h1, tiles, s);
   }
 }
 
