@@ -92,6 +92,50 @@ def cpu_baseline(cnf, R, lr, budget_s: float):
                       f"{t:.1f} s", "seconds": round(t, 2)}
 
 
+def batched_vs_plain(steps: int):
+    """The uneven batch of 4,096 formulas (R=32): every formula in each launch
+    (the batched schedule, replayed from a captured graph) against one formula
+    at a time with a launch per pass per step and no graph, same kernels,
+    same steps, both from the same initial state in HBM."""
+    import torch
+
+    from paper_2603_28796_amd import inputs as I
+    from paper_2603_28796_amd.galsat import Problem
+
+    w = I.WORKLOADS["batch4096"]
+    t0 = time.perf_counter()
+    cnf = w.make()
+    log(f"[bench] batch workload: F={cnf.F} n={cnf.n} L={cnf.L} "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    R = w.restarts
+    out = {"workload": w.key, "formulas": cnf.F, "restarts": R, "steps": steps}
+    x0 = None
+    for name, sched, graph in (("batched", "general", True), ("plain", "plain", False)):
+        prob = Problem(cnf, R, lr=w.lr, schedule=sched, use_graph=graph)
+        if x0 is None:
+            x0 = prob.init_state(I.SEED_BASE + 4)
+        x = x0.clone()
+        lt = torch.empty((steps, cnf.F, R), dtype=torch.float32, device="cuda")
+        ut = torch.empty((steps, cnf.F, R), dtype=torch.int32, device="cuda")
+        prob.step(x, 1, loss_trace=lt[:1], unsat_trace=ut[:1], trace=True)  # warm-up
+        x = x0.clone()
+        if graph:
+            prob.prepare(x, steps, loss_trace=lt, unsat_trace=ut)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        prob.step(x, steps, loss_trace=lt, unsat_trace=ut, trace=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[f"{name}_ms_per_step"] = ms / steps
+        out[f"{name}_lit_evals_per_s"] = R * cnf.L * steps / (ms / 1e3)
+        log(f"[bench] {name}: {ms / steps:.3f} ms/step")
+        prob.close()
+    out["speedup"] = out["plain_ms_per_step"] / out["batched_ms_per_step"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +147,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel run")
+    ap.add_argument("--graph", type=int, default=1, help="replay the step loop from a hipGraph")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="steps of the batched vs one-formula-at-a-time comparison (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -126,7 +173,8 @@ def main():
     R = w.restarts
     partials = args.partials or {0: "auto", 1: "store", 2: "recompute"}[w.recompute]
     torch.cuda.set_device(0)
-    prob = Problem(cnf, R, lr=w.lr, partials=partials, plan_override=args.plan)
+    prob = Problem(cnf, R, lr=w.lr, partials=partials, plan_override=args.plan,
+                   use_graph=bool(args.graph))
     info = prob.info()
     log(f"[bench] plan: {info}")
     x = prob.init_state(I.SEED_BASE + 2)
@@ -138,6 +186,8 @@ def main():
     if W > 0:
         prob.step(x, W, loss_trace=lt[:W], unsat_trace=ut[:W], trace=True)
         prob.round_check(x)
+    if args.graph:
+        prob.prepare(x, K, loss_trace=lt[:K], unsat_trace=ut[:K])  # capture outside the timing
     torch.cuda.synchronize()
     log(f"[bench] warmup {W} steps done")
 
@@ -166,14 +216,22 @@ def main():
         log(f"[bench] kernel times: {kernels}")
         launches, tot = kernels.get("var_pass", (0, 0.0))
         if launches:
+            # the pass may be split into several launches per step (restart
+            # tile groups): each launch moves its share of the step's bytes
+            per_step = launches / K
             avg_ms = tot / launches
-            ab = algorithmic_bytes(cnf, R, info, "sgd")
+            ab = algorithmic_bytes(cnf, R, info, "sgd") / per_step
             achieved = ab / (avg_ms / 1e3) / 1e9
             traffic = read_traffic(w.key, "var_pass")
             roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "traffic": traffic, "kernel": "k_var_pass",
-                        "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_ms, 5)}
+                        "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_ms, 5),
+                        "launches_per_step": per_step}
+
+    batch = None
+    if args.batch_steps > 0:
+        batch = batched_vs_plain(args.batch_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -200,6 +258,7 @@ def main():
                    "restarts_per_lane": info["restarts_per_lane"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_vs_plain": batch,
         "kernel_ms": {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 5)}
                       for k, v in (kernels or {}).items()},
     }

@@ -183,6 +183,14 @@ galsat_status galsat_loss_grad(galsat_handle h, const float* x, int32_t ldx, con
 galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, float* opt_state, int32_t steps,
                           float* loss_trace, int32_t* unsat_trace, void* stream);
 
+/* For a handle created with use_graph: captures and instantiates the graph
+ * of galsat_step with exactly these arguments without running it, so the
+ * next galsat_step call with the same arguments only replays it.  Returns
+ * GALSAT_EUNSUPPORTED when the call would run eagerly (no use_graph, Adam,
+ * or profiling enabled). */
+galsat_status galsat_step_prepare(galsat_handle h, float* x, int32_t ldx, float* opt_state,
+                                  int32_t steps, float* loss_trace, int32_t* unsat_trace);
+
 /* Rounds x (x > 0.5 -> 1; an x that is already 0/1 is used as given),
  * counts unsatisfied clauses exactly per (formula, restart) with wavefront
  * ballot and popcount, and picks per formula the restart with the fewest

@@ -29,6 +29,9 @@ thread_local std::string g_create_error;
 
 constexpr int kDefaultRecomputeMaxLen = 8;
 constexpr int kTargetBlocks = 2048;  // blocks per general-pass launch (256 CUs x 8)
+constexpr int64_t kCacheBudgetBytes = 256ll << 20;  // state rows one launch may gather from
+constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
+constexpr int64_t kXcdChunks = 160;                 // workgroups resident on one XCD (about)
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -119,6 +122,7 @@ struct galsat_ctx {
   int64_t stored = 0;
   int schedule = GALSAT_SCHED_GENERAL;
   Tile tile;
+  int tgroup = 1;    // restart tiles per launch of a gradient pass
   int32_t ld = 0;    // internal state row stride (floats)
   int64_t ldD = 0;
   int adam_t = 0;
@@ -134,8 +138,10 @@ struct galsat_ctx {
   // device tables
   int32_t *clause_ptr = nullptr, *clause_lits = nullptr, *var_ptr = nullptr, *var_occ = nullptr;
   int4* occ4 = nullptr;
+  int4* occx = nullptr;
   int32_t *lit_dslot = nullptr, *var_formula = nullptr, *stored_ids = nullptr;
-  int32_t *vch_beg = nullptr, *vch_end = nullptr, *vch_row = nullptr;
+  int32_t *vch_beg = nullptr, *vch_end = nullptr, *vch_row = nullptr, *vch_order = nullptr;
+  int32_t n_vorder = 0;  // entries of vch_order (0: launch chunks in index order)
   int32_t *sch_beg = nullptr, *sch_end = nullptr, *sch_row = nullptr;
   int32_t *segch_beg = nullptr, *segch_end = nullptr, *segch_row = nullptr;
   int32_t *ach_beg = nullptr, *ach_end = nullptr;
@@ -183,7 +189,24 @@ struct galsat_ctx {
     recs.clear();
   }
 
+  // captured step sequence of galsat_step (use_graph)
+  struct GraphKey {
+    float* x;
+    int32_t ldx, steps;
+    float* loss_trace;
+    int32_t* unsat_trace;
+    bool operator==(const GraphKey& o) const {
+      return x == o.x && ldx == o.ldx && steps == o.steps && loss_trace == o.loss_trace &&
+             unsat_trace == o.unsat_trace;
+    }
+  };
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  GraphKey graph_key{};
+
   ~galsat_ctx() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     release_records();
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
@@ -311,8 +334,8 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
   return s;
 }
 
-// Parses "key=value,key=value" plan overrides: lpi, rpl, krec.
-void apply_override(const char* spec, int* lpi, int* rpl, int* krec) {
+// Parses "key=value,key=value" plan overrides: lpi, rpl, krec, tg.
+void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -327,6 +350,7 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec) {
       if (k == "lpi") *lpi = v;
       else if (k == "rpl") *rpl = v;
       else if (k == "krec") *krec = v;
+      else if (k == "tg") *tg = v;
     }
     pos = comma + 1;
   }
@@ -495,8 +519,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   (void)hipGetDevice(&h->device);
 
   // ---- plan: which clauses recompute their partials in the variable pass
-  int lpi_o = 0, rpl_o = 0, krec_o = -1;
-  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o);
+  int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0;
+  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o);
   int32_t krec;
   if (opt.partials == GALSAT_PARTIALS_STORE) krec = -1;           // every clause stores
   else if (opt.partials == GALSAT_PARTIALS_RECOMPUTE) krec = kmax;
@@ -505,6 +529,15 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   h->tile = choose_tile(R, 4);
   if (lpi_o == 4 || lpi_o == 8 || lpi_o == 16 || lpi_o == 32 || lpi_o == 64) h->tile.lpi = lpi_o;
   if ((rpl_o == 1 || rpl_o == 2 || rpl_o == 4) && R % rpl_o == 0) h->tile.rpl = rpl_o;
+  // Restart tiles per launch: keep the state rows a launch gathers from
+  // (n x tiles x tile x 4 B) within a share of the 256 MB last-level cache.
+  {
+    const int tiles_all = (R + h->tile.tile() - 1) / h->tile.tile();
+    const int64_t tile_bytes = std::max<int64_t>(1, (int64_t)n * h->tile.tile() * 4);
+    int tg = (int)std::max<int64_t>(1, kCacheBudgetBytes / tile_bytes);
+    if (tg_o > 0) tg = tg_o;
+    h->tgroup = std::min(tg, tiles_all);
+  }
   h->ld = (int32_t)round_up(R, 4);
   h->ldD = round_up(R, 4);
   auto count_stored = [&](int32_t kr) {
@@ -535,6 +568,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // variable's stored partials are contiguous.
   // filled completely below, so left uninitialised
   std::unique_ptr<int4[]> occ4(new int4[(size_t)L + 1]);
+  const bool need_x = krec >= 5 && kmax >= 5;  // some inline record holds 4 to 7 others
+  std::unique_ptr<int4[]> occx(new int4[need_x ? (size_t)L + 1 : 1]);
   std::unique_ptr<int32_t[]> occ_cost(new int32_t[(size_t)L + 1]);
   std::unique_ptr<int32_t[]> lit_dslot(new int32_t[stored > 0 ? (size_t)L + 1 : 1]);
   {
@@ -556,21 +591,23 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       int64_t d = sbase[v];
       for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
         const int32_t p = vo[q], t = clause_of[p], k = cp[t + 1] - cp[t];
+        const int32_t sign_first = ((cl[p] & 1) << 3) | ((p == cp[t]) ? 16 : 0);
         if (k > krec) {
-          occ4[q] = make_int4(2 << 4, (int32_t)d, 0, 0);
+          occ4[q] = make_int4(2 << 5, (int32_t)d, 0, 0);
           occ_cost[q] = 1;
           lit_dslot[p] = (int32_t)d;
           ++d;
-        } else if (k <= 4) {
-          int32_t codes[3] = {2 * v, 2 * v, 2 * v};
+        } else if (k <= 8) {
+          int32_t codes[7] = {2 * v, 2 * v, 2 * v, 2 * v, 2 * v, 2 * v, 2 * v};
           int32_t c = 0;
           for (int32_t i = cp[t]; i < cp[t + 1]; ++i)
             if (i != p) codes[c++] = cl[i];
-          const int32_t hdr = (k - 1) | ((cl[p] & 1) << 2) | ((p == cp[t]) ? 8 : 0);
-          occ4[q] = make_int4(hdr, codes[0], codes[1], codes[2]);
+          occ4[q] = make_int4((k - 1) | sign_first, codes[0], codes[1], codes[2]);
+          if (need_x) occx[q] = make_int4(codes[3], codes[4], codes[5], codes[6]);
           occ_cost[q] = std::max(1, k - 1);
         } else {
-          occ4[q] = make_int4(1 << 4, t, p, 0);
+          occ4[q] = make_int4((1 << 5) | sign_first, t, p, 0);
+          if (need_x) occx[q] = make_int4(0, 0, 0, 0);
           occ_cost[q] = k - 1;
         }
       }
@@ -595,7 +632,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   const int tiles = (R + h->tile.tile() - 1) / h->tile.tile();
   const int64_t chunks_target = std::max<int64_t>(1, kTargetBlocks / std::max(1, tiles));
   const int ipb = kBlock / h->tile.lpi;
-  std::vector<int32_t> heavy, heavy_sbeg{0}, seg_var, seg_q0, seg_q1;
+  std::vector<int32_t> heavy, heavy_sbeg{0}, seg_var, seg_q0, seg_q1, vorder;
   std::vector<int32_t> heavy_f_first((size_t)F + 1, 0);
   {
     std::vector<int64_t> vcost((size_t)n, 1);
@@ -610,13 +647,32 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     Chunks vc, sc;
     vc.f_first.assign((size_t)F + 1, 0);
     sc.f_first.assign((size_t)F + 1, 0);
+    const bool per_formula = opt.schedule == GALSAT_SCHED_PLAIN;
+    std::vector<int64_t> fcost((size_t)F, 0);
     for (int32_t f = 0; f < F; ++f) {
       vc.f_first[f] = vc.count();
       heavy_f_first[f] = (int32_t)heavy.size();
       int32_t cb = fvb[f];
       int64_t acc = 0;
+      // one formula per launch (PLAIN): size its chunks as if it were the
+      // whole problem, so each launch still spreads over the chip.  Which
+      // variables are split does not change, so every gradient is summed in
+      // the same order as in the all-formula plan.
+      int64_t target_f = target;
+      const int64_t item_cap_f = item_cap;
+      int64_t cost_f = 0;
+      for (int32_t v = fvb[f]; v < fvb[f + 1]; ++v) cost_f += vcost[v];
+      fcost[f] = cost_f;
+      if (per_formula) {
+        target_f = std::max<int64_t>(64, cost_f / chunks_target);
+      } else if (F > 1) {
+        // many formulas in one launch: about kXcdChunks chunks per formula,
+        // so the workgroups resident on one XCD work on one formula at a
+        // time and its state stays in that XCD's L2 (see the launch order)
+        target_f = std::max<int64_t>(64, cost_f / kXcdChunks);
+      }
       for (int32_t v = fvb[f]; v < fvb[f + 1]; ++v) {
-        if (vcost[v] > item_cap && vp[v + 1] - vp[v] > 1) {
+        if (vcost[v] > item_cap_f && vp[v + 1] - vp[v] > 1) {
           if (v > cb) { vc.beg.push_back(cb); vc.end.push_back(v); }
           cb = v + 1;
           acc = 0;
@@ -625,7 +681,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
           int32_t q0 = vp[v];
           for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
             sacc += occ_cost[q];
-            if (sacc >= item_cap || q + 1 == vp[v + 1]) {
+            if (sacc >= item_cap_f || q + 1 == vp[v + 1]) {
               seg_var.push_back(v);
               seg_q0.push_back(q0);
               seg_q1.push_back(q + 1);
@@ -637,7 +693,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
           continue;
         }
         acc += vcost[v];
-        if (acc >= target) {
+        if (acc >= target_f) {
           vc.beg.push_back(cb);
           vc.end.push_back(v + 1);
           cb = v + 1;
@@ -652,7 +708,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       int64_t sacc = 0;
       for (int32_t sg = s_lo; sg < s_hi; ++sg) {
         for (int32_t q = seg_q0[sg]; q < seg_q1[sg]; ++q) sacc += occ_cost[q];
-        if (sacc >= target || sg + 1 == s_hi) {
+        if (sacc >= target_f || sg + 1 == s_hi) {
           sc.beg.push_back(sb);
           sc.end.push_back(sg + 1);
           sb = sg + 1;
@@ -662,6 +718,29 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     }
     vc.f_first[F] = vc.count();
     sc.f_first[F] = sc.count();
+    // XCD-aware launch order of the variable chunks (several formulas per
+    // launch): workgroups are dealt to the 8 XCDs round-robin by index, so
+    // formulas are split into 8 groups of balanced cost (longest first) and
+    // group x's chunks are placed at indices x, x + 8, x + 16, ...; padding
+    // indices (-1) do nothing.
+    if (F > 1 && !per_formula) {
+      std::vector<int32_t> ford(F);
+      for (int32_t f = 0; f < F; ++f) ford[f] = f;
+      std::stable_sort(ford.begin(), ford.end(),
+                       [&](int32_t a2, int32_t b2) { return fcost[a2] > fcost[b2]; });
+      std::vector<int64_t> load(kXcds, 0);
+      std::vector<std::vector<int32_t>> lists(kXcds);
+      for (int32_t f : ford) {
+        const int gsel = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[gsel] += fcost[f];
+        for (int32_t cid = vc.f_first[f]; cid < vc.f_first[f + 1]; ++cid) lists[gsel].push_back(cid);
+      }
+      size_t longest = 0;
+      for (auto& l : lists) longest = std::max(longest, l.size());
+      vorder.assign(longest * kXcds, -1);
+      for (int gsel = 0; gsel < kXcds; ++gsel)
+        for (size_t i = 0; i < lists[gsel].size(); ++i) vorder[i * kXcds + gsel] = lists[gsel][i];
+    }
     heavy_f_first[F] = (int32_t)heavy.size();
     h->vch = vc;
     h->segch = sc;
@@ -726,9 +805,12 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UPP(clause_lits, cl, L);
   UPP(var_ptr, vp, n + 1);
 #undef UPP
-  if ((he = c->upload(&c->occ4, occ4.get(), (size_t)L, s)) != hipSuccess)
+  if ((he = c->upload(&c->occ4, occ4.get(), (size_t)L, s)) != hipSuccess ||
+      (need_x && (he = c->upload(&c->occx, occx.get(), (size_t)L, s)) != hipSuccess))
     return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
                        std::string("upload occurrence records: ") + hipGetErrorString(he));
+  if (!need_x && (he = c->alloc(&c->occx, 1)) != hipSuccess)
+    return create_fail(GALSAT_EDEVICE, "allocate record words");
   if (stored > 0 && (he = c->upload(&c->lit_dslot, lit_dslot.get(), (size_t)L, s)) != hipSuccess)
     return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
                        std::string("upload stored rows: ") + hipGetErrorString(he));
@@ -737,6 +819,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(vch_beg, c->vch.beg);
   UP(vch_end, c->vch.end);
   UP(vch_row, vrow);
+  UP(vch_order, vorder);
+  c->n_vorder = (int32_t)vorder.size();
   UP(sch_beg, c->sch.beg);
   UP(sch_end, c->sch.end);
   UP(sch_row, srow);
@@ -843,6 +927,7 @@ VarPassArgs var_args(const galsat_ctx* h) {
   VarPassArgs a{};
   a.var_ptr = h->var_ptr;
   a.occ = h->occ4;
+  a.occx = h->occx;
   a.clause_ptr = h->clause_ptr;
   a.clause_lits = h->clause_lits;
   a.chunk_vbeg = h->vch_beg;
@@ -889,46 +974,68 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
     va.inv_c2 = 1.0 / (1.0 - std::pow((double)h->opt.beta2, tt));
   }
   const int sc0 = h->sch.f_first[f0], sc1 = h->sch.f_first[f1];
-  if (h->stored > 0 && sc1 > sc0) {
-    ClausePassArgs ca{};
-    ca.clause_ptr = h->clause_ptr;
-    ca.clause_lits = h->clause_lits;
-    ca.lit_dslot = h->lit_dslot;
-    ca.clause_ids = h->stored_ids;
-    ca.chunk_cbeg = h->sch_beg;
-    ca.chunk_cend = h->sch_end;
-    ca.chunk_row = h->sch_row;
-    ca.chunk_base = sc0;
-    ca.x = x;
-    ca.ldx = ldx;
-    ca.D = h->D;
-    ca.ldD = h->ldD;
-    ca.loss_part = h->loss_part;
-    ca.unsat_part = h->unsat_part;
-    ca.R = h->R;
-    ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
-    GS_HIP(h, launch_clause_pass(ca, true, t, sc1 - sc0, s), "clause pass");
-  }
   const int vc0 = h->vch.f_first[f0], vc1 = h->vch.f_first[f1];
-  va.chunk_base = vc0;
-  {
-    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
-    GS_HIP(h, launch_var_pass(va, mode, t, vc1 - vc0, s), "var pass");
-  }
   const int gc0 = h->segch.f_first[f0], gc1 = h->segch.f_first[f1];
-  if (gc1 > gc0) {
-    VarPassArgs sa = va;
-    sa.chunk_vbeg = h->segch_beg;
-    sa.chunk_vend = h->segch_end;
-    sa.chunk_row = h->segch_row;
-    sa.chunk_base = gc0;
+  const int tiles_all = (h->R + t.tile() - 1) / t.tile();
+  // the planned group size applies to the planned tile; a fallback tile
+  // (unaligned caller buffers) keeps the same restart span per launch
+  const int tg = std::max(1, h->tgroup * h->tile.tile() / t.tile());
+  for (int tb = 0; tb < tiles_all; tb += tg) {
+    const int tc = std::min(tg, tiles_all - tb);
+    if (h->stored > 0 && sc1 > sc0) {
+      ClausePassArgs ca{};
+      ca.clause_ptr = h->clause_ptr;
+      ca.clause_lits = h->clause_lits;
+      ca.lit_dslot = h->lit_dslot;
+      ca.clause_ids = h->stored_ids;
+      ca.chunk_cbeg = h->sch_beg;
+      ca.chunk_cend = h->sch_end;
+      ca.chunk_row = h->sch_row;
+      ca.chunk_base = sc0;
+      ca.tile_base = tb;
+      ca.tile_count = tc;
+      ca.x = x;
+      ca.ldx = ldx;
+      ca.D = h->D;
+      ca.ldD = h->ldD;
+      ca.loss_part = h->loss_part;
+      ca.unsat_part = h->unsat_part;
+      ca.R = h->R;
+      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
+      GS_HIP(h, launch_clause_pass(ca, true, t, sc1 - sc0, s), "clause pass");
+    }
+    va.tile_base = tb;
+    va.tile_count = tc;
+    va.chunk_vbeg = h->vch_beg;
+    va.chunk_vend = h->vch_end;
+    va.chunk_row = h->vch_row;
+    va.chunk_base = vc0;
+    int vblocks = vc1 - vc0;
+    va.chunk_order = nullptr;
+    if (h->n_vorder > 0 && f0 == 0 && f1 == h->F) {
+      va.chunk_order = h->vch_order;
+      va.chunk_base = 0;
+      vblocks = h->n_vorder;
+    }
     {
       ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
-      GS_HIP(h, launch_var_seg(sa, t, gc1 - gc0, s), "segment pass");
+      GS_HIP(h, launch_var_pass(va, mode, t, vblocks, s), "var pass");
     }
-    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
-    GS_HIP(h, launch_heavy_finish(va, mode, t, h->heavy_f_first[f0], h->heavy_f_first[f1], s),
-           "split-variable finish");
+    va.chunk_order = nullptr;
+    if (gc1 > gc0) {
+      VarPassArgs sa = va;
+      sa.chunk_vbeg = h->segch_beg;
+      sa.chunk_vend = h->segch_end;
+      sa.chunk_row = h->segch_row;
+      sa.chunk_base = gc0;
+      {
+        ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+        GS_HIP(h, launch_var_seg(sa, t, gc1 - gc0, s), "segment pass");
+      }
+      ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+      GS_HIP(h, launch_heavy_finish(va, mode, t, h->heavy_f_first[f0], h->heavy_f_first[f1], s),
+             "split-variable finish");
+    }
   }
   return GALSAT_OK;
 }
@@ -1000,29 +1107,28 @@ galsat_status general_step(galsat_ctx* h, Tile t, const float* xin, float* xout,
 
 }  // namespace
 
-extern "C" galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, float* opt_state,
-                                     int32_t steps, float* loss_trace, int32_t* unsat_trace,
-                                     void* stream) {
-  GS_CHECK_HANDLE(h);
-  if (!x && h->n > 0) return h->fail(GALSAT_EINVAL, "x is NULL");
-  if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
-  if (steps < 0) return h->fail(GALSAT_EINVAL, "steps must be >= 0");
+namespace {
+
+// Enqueues `steps` iterations.  When the caller's state already has the
+// internal layout the iterations ping-pong between it and one internal
+// buffer, arranged so the last one lands in x (one copy for an odd count,
+// none for an even one); otherwise x is copied in and out.
+galsat_status enqueue_steps(galsat_ctx* h, Tile t, float* x, int32_t ldx, float* mom, float* vel,
+                            int32_t steps, float* loss_trace, int32_t* unsat_trace,
+                            hipStream_t s) {
   const bool adam = h->opt.optimizer == GALSAT_OPT_ADAM;
-  if (adam && !opt_state && h->n > 0) return h->fail(GALSAT_EINVAL, "Adam needs opt_state");
-  if (steps == 0) return GALSAT_OK;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t FR = (int64_t)h->F * h->R;
-  float* mom = adam ? opt_state : nullptr;
-  float* vel = adam ? opt_state + (int64_t)h->n * ldx : nullptr;
-  // the internal state is aligned for the planned tile; the caller's Adam
-  // moments may not be
-  const Tile t = adam ? tile_for(h, mom, ldx, vel, ldx) : h->tile;
-  {
+  const bool direct = ldx == h->ld && aligned_for(x, ldx, h->tile.rpl);
+  float *cur, *nxt;
+  if (direct && steps % 2 == 0) {
+    cur = x;
+    nxt = h->xa;
+  } else {
     ProfScope _ps(h, GALSAT_K_COPY, s);
     GS_HIP(h, launch_copy_state(x, ldx, h->xa, h->ld, h->n, h->R, s), "copy in");
+    cur = h->xa;
+    nxt = direct ? x : h->xb;
   }
-  float* cur = h->xa;
-  float* nxt = h->xb;
   for (int32_t k = 0; k < steps; ++k) {
     float* lrow = loss_trace ? loss_trace + k * FR : nullptr;
     int32_t* urow = unsat_trace ? unsat_trace + k * FR : nullptr;
@@ -1038,11 +1144,87 @@ extern "C" galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, flo
     if (adam) h->adam_t++;
     std::swap(cur, nxt);
   }
-  {
+  if (cur != x) {
     ProfScope _ps(h, GALSAT_K_COPY, s);
     GS_HIP(h, launch_copy_state(cur, h->ld, x, ldx, h->n, h->R, s), "copy out");
   }
   return GALSAT_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Graph replay: the whole call (every step's launches) is captured once on a
+// private stream and replayed on the caller's stream while the call's
+// arguments stay the same.  Adam's bias correction changes the launch
+// arguments every step, and profiling records events, so both run eagerly.
+galsat_status capture_steps(galsat_ctx* h, Tile t, float* x, int32_t ldx, int32_t steps,
+                            float* loss_trace, int32_t* unsat_trace) {
+  const galsat_ctx::GraphKey key{x, ldx, steps, loss_trace, unsat_trace};
+  if (h->graph_exec && h->graph_key == key) return GALSAT_OK;
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  h->graph_exec = nullptr;
+  if (!h->cap_stream)
+    GS_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "capture stream");
+  GS_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
+  galsat_status st = enqueue_steps(h, t, x, ldx, nullptr, nullptr, steps, loss_trace, unsat_trace,
+                                   h->cap_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+  if (st != GALSAT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return h->dev_fail(e, "end capture");
+  e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    h->graph_exec = nullptr;
+    return h->dev_fail(e, "graph instantiate");
+  }
+  h->graph_key = key;
+  return GALSAT_OK;
+}
+
+}  // namespace
+
+extern "C" galsat_status galsat_step_prepare(galsat_handle h, float* x, int32_t ldx,
+                                             float* opt_state, int32_t steps, float* loss_trace,
+                                             int32_t* unsat_trace) {
+  GS_CHECK_HANDLE(h);
+  if (!x && h->n > 0) return h->fail(GALSAT_EINVAL, "x is NULL");
+  if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
+  if (steps <= 0) return h->fail(GALSAT_EINVAL, "steps must be >= 1");
+  (void)opt_state;
+  if (!h->opt.use_graph || h->opt.optimizer == GALSAT_OPT_ADAM || h->prof)
+    return h->fail(GALSAT_EUNSUPPORTED, "this handle runs galsat_step eagerly");
+  return capture_steps(h, h->tile, x, ldx, steps, loss_trace, unsat_trace);
+}
+
+extern "C" galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, float* opt_state,
+                                     int32_t steps, float* loss_trace, int32_t* unsat_trace,
+                                     void* stream) {
+  GS_CHECK_HANDLE(h);
+  if (!x && h->n > 0) return h->fail(GALSAT_EINVAL, "x is NULL");
+  if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
+  if (steps < 0) return h->fail(GALSAT_EINVAL, "steps must be >= 0");
+  const bool adam = h->opt.optimizer == GALSAT_OPT_ADAM;
+  if (adam && !opt_state && h->n > 0) return h->fail(GALSAT_EINVAL, "Adam needs opt_state");
+  if (steps == 0) return GALSAT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float* mom = adam ? opt_state : nullptr;
+  float* vel = adam ? opt_state + (int64_t)h->n * ldx : nullptr;
+  // the internal state is aligned for the planned tile; the caller's Adam
+  // moments may not be
+  const Tile t = adam ? tile_for(h, mom, ldx, vel, ldx) : h->tile;
+  if (h->opt.use_graph && !adam && !h->prof) {
+    galsat_status st = capture_steps(h, t, x, ldx, steps, loss_trace, unsat_trace);
+    if (st != GALSAT_OK) return st;
+    GS_HIP(h, hipGraphLaunch(h->graph_exec, s), "graph launch");
+    return GALSAT_OK;
+  }
+  return enqueue_steps(h, t, x, ldx, mom, vel, steps, loss_trace, unsat_trace, s);
 }
 
 extern "C" galsat_status galsat_round_check(galsat_handle h, const float* x, int32_t ldx,

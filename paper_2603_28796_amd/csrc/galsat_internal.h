@@ -27,11 +27,13 @@ struct Tile {
 struct VarPassArgs {
   const int32_t* var_ptr;
   const int4* occ;              // [L] occurrence record of each variable-major slot
+  const int4* occx;             // [L] second record word (5 to 8 literal clauses)
   const int32_t* clause_ptr;
   const int32_t* clause_lits;
   const int32_t* chunk_vbeg;    // [chunks] item range of each chunk (variables or segments)
   const int32_t* chunk_vend;
   const int32_t* chunk_row;     // [chunks] partial-sum row of each chunk
+  const int32_t* chunk_order;   // [blocks] chunk of each workgroup (-1: none), or null
   const int32_t* seg_var;       // [segments] variable of each segment of a split variable
   const int32_t* seg_q0;        // [segments] occurrence range of the segment
   const int32_t* seg_q1;
@@ -40,6 +42,8 @@ struct VarPassArgs {
   const int32_t* heavy_sbeg;    // [heavy+1] segment range of each split variable
   const int32_t* var_formula;   // [n] formula of each variable (upstream scaling)
   int32_t chunk_base;           // first chunk of this launch
+  int32_t tile_base;            // first restart tile of this launch
+  int32_t tile_count;           // restart tiles of this launch (0: all from tile_base)
   const float* x;
   int32_t ldx;
   float* out;                   // next state (update modes) or gradient (grad mode)
@@ -69,6 +73,8 @@ struct ClausePassArgs {
   const int32_t* chunk_cend;
   const int32_t* chunk_row;     // [chunks] partial-sum row, or null for row = chunk
   int32_t chunk_base;
+  int32_t tile_base;            // first restart tile of this launch
+  int32_t tile_count;           // restart tiles of this launch (0: all from tile_base)
   const float* x;
   int32_t ldx;
   float* D;

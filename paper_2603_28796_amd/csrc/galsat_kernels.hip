@@ -64,6 +64,18 @@ __device__ __forceinline__ int uniform(int v) {
   return v;
 }
 
+// Loads from the read-only plan tables (CSR, occurrence records, chunk
+// tables), which no kernel writes: reading them through the constant
+// address space lets wave-uniform loads become scalar loads.
+__device__ __forceinline__ int ldc(const int32_t* p, int64_t i) {
+  return ((const __attribute__((address_space(4))) int32_t*)p)[i];
+}
+
+__device__ __forceinline__ int4 ldc4(const int4* p, int64_t i) {
+  const int32_t* b = reinterpret_cast<const int32_t*>(p) + 4 * i;
+  return make_int4(ldc(b, 0), ldc(b, 1), ldc(b, 2), ldc(b, 3));
+}
+
 __device__ __forceinline__ float clamp01(double y) {
   y = y < 0.0 ? 0.0 : y;
   y = y > 1.0 ? 1.0 : y;
@@ -74,7 +86,7 @@ __device__ __forceinline__ float clamp01(double y) {
 // and write one row of partial sums per (chunk, restart).
 template <int LPI, int RPL>
 __device__ __forceinline__ void block_partials(const double (&lsum)[RPL], const int (&usum)[RPL],
-                                               int64_t row, int R, double* loss_part,
+                                               int64_t row, int tile, int R, double* loss_part,
                                                int32_t* unsat_part) {
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
@@ -94,7 +106,7 @@ __device__ __forceinline__ void block_partials(const double (&lsum)[RPL], const 
       acc += s_l[s * RT + i];
       uacc += s_u[s * RT + i];
     }
-    const int r = blockIdx.y * RT + i;
+    const int r = tile * RT + i;
     if (r < R) {
       loss_part[row * R + r] = acc;
       unsat_part[row * R + r] = uacc;
@@ -113,21 +125,28 @@ __device__ __forceinline__ void block_partials(const double (&lsum)[RPL], const 
 // accounts for that clause's U_t and its rounded satisfaction, so each
 // clause enters the loss and the unsat count exactly once.
 
-// Occurrence records (one int4 per variable-major slot, see the host's
-// plan): x = header, y/z/w = payload.
-//   SHORT   recomputed clause of at most 4 literals: header bits 0-1 hold the
-//           number of other literals (0..3), bit 2 the own literal's sign
-//           (1 = negated), bit 3 whether the own literal is the clause's
-//           first; y, z, w the other literals' codes (unused ones repeat
-//           the own variable, so every load stays in bounds).
-//   GENERAL recomputed longer clause: y = clause id, z = own position.
-//   STORED  partial stored by the clause pass: y = stored row.
-constexpr int kRecShort = 0, kRecStored = 2;  // kind 1 is GENERAL
-__device__ __forceinline__ int rec_kind(int hdr) { return hdr >> 4; }
+// Occurrence records: per variable-major slot two int4 words, occ[q] and
+// occx[q] (the second is read only for clauses of 5 to 8 literals).
+// Header (occ[q].x): bits 0-2 the number of other literals (0..7), bit 3
+// the own literal's sign (1 = negated), bit 4 whether the own literal is
+// its clause's first, bits 5-6 the kind:
+//   INLINE  recomputed clause of at most 8 literals; the other literals'
+//           codes are occ[q].y, .z, .w, occx[q].x, .y, .z, .w (unused
+//           entries repeat the own variable, so every load stays in
+//           bounds);
+//   GENERAL recomputed longer clause: occ[q].y = clause id, .z = own
+//           position in clause_lits;
+//   STORED  partial stored by the clause pass: occ[q].y = stored row.
+constexpr int kRecInline = 0, kRecStored = 2;  // kind 1 is GENERAL
+__device__ __forceinline__ int rec_kind(int hdr) { return hdr >> 5; }
+__device__ __forceinline__ int rec_nother(int hdr) { return hdr & 7; }
+__device__ __forceinline__ bool rec_neg(int hdr) { return (hdr & 8) != 0; }
+__device__ __forceinline__ bool rec_first(int hdr) { return (hdr & 16) != 0; }
 
 // Contribution of one occurrence whose other-literal product is prod: the
 // slope of the own factor times prod, and, for the clause's first literal,
-// the clause's U and rounded satisfaction.
+// the clause's U and rounded satisfaction (any_true: some other literal is
+// true under rounding).
 template <int RPL>
 __device__ __forceinline__ void add_occurrence(bool own_neg, bool first, const float (&prod)[RPL],
                                                const bool (&any_true)[RPL], const float (&xv)[RPL],
@@ -145,43 +164,120 @@ __device__ __forceinline__ void add_occurrence(bool own_neg, bool first, const f
   }
 }
 
-// Four consecutive SHORT occurrences: all row gathers are issued before any
-// product is formed, so a wave keeps up to twelve loads in flight.
-template <int RPL>
-__device__ __forceinline__ void short4(const VarPassArgs& a, const int4 (&o)[4], int r0,
-                                       const float (&xv)[RPL], double (&g)[RPL],
-                                       double (&lsum)[RPL], int (&usum)[RPL]) {
-  float y[4][3][RPL];
+// Product of the first `nother` of NO gathered rows y[c] (codes[c]) and,
+// when `first`, whether any of them is true under rounding.
+template <int RPL, int NO>
+__device__ __forceinline__ void combine(const int (&codes)[NO], const float (&y)[NO][RPL],
+                                        int nother, bool first, float (&prod)[RPL],
+                                        bool (&any_true)[RPL]) {
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    prod[j] = 1.0f;
+    any_true[j] = false;
+#pragma unroll
+    for (int c = 0; c < NO; ++c) prod[j] *= c < nother ? lit_factor(codes[c], y[c][j]) : 1.0f;
+  }
+  if (first) {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+#pragma unroll
+      for (int c = 0; c < NO; ++c)
+        any_true[j] = any_true[j] || (c < nother && lit_true(codes[c], y[c][j]));
+  }
+}
+
+// Four consecutive INLINE occurrences with at most NO (<= 3) other literals
+// each: every row gather is issued before any product is formed, so a wave
+// keeps up to 4 * NO loads in flight.
+template <int RPL, int NO>
+__device__ __forceinline__ void inline4(const VarPassArgs& a, const int4 (&o)[4], int r0,
+                                        const float (&xv)[RPL], double (&g)[RPL],
+                                        double (&lsum)[RPL], int (&usum)[RPL]) {
+  float y[4][NO][RPL];
+  int codes[4][NO];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    load_row<RPL>(a.x + (int64_t)(o[k].y >> 1) * a.ldx + r0, y[k][0]);
-    load_row<RPL>(a.x + (int64_t)(o[k].z >> 1) * a.ldx + r0, y[k][1]);
-    load_row<RPL>(a.x + (int64_t)(o[k].w >> 1) * a.ldx + r0, y[k][2]);
+    const int all[3] = {o[k].y, o[k].z, o[k].w};
+#pragma unroll
+    for (int c = 0; c < NO; ++c) {
+      codes[k][c] = all[c];
+      load_row<RPL>(a.x + (int64_t)(all[c] >> 1) * a.ldx + r0, y[k][c]);
+    }
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int hdr = o[k].x, nother = hdr & 3;
-    const int codes[3] = {o[k].y, o[k].z, o[k].w};
+    const int hdr = o[k].x;
     float prod[RPL];
     bool any_true[RPL];
+    combine<RPL, NO>(codes[k], y[k], rec_nother(hdr), rec_first(hdr), prod, any_true);
+    add_occurrence<RPL>(rec_neg(hdr), rec_first(hdr), prod, any_true, xv, g, lsum, usum);
+  }
+}
+
+// One INLINE occurrence of up to 7 other literals, all gathers in flight.
+template <int RPL>
+__device__ __forceinline__ void inline_one(const VarPassArgs& a, const int4 o, int q, int r0,
+                                           const float (&xv)[RPL], double (&g)[RPL],
+                                           double (&lsum)[RPL], int (&usum)[RPL]) {
+  const int hdr = o.x, nother = rec_nother(hdr);
+  float prod[RPL];
+  bool any_true[RPL];
+  if (nother <= 3) {
+    const int codes[3] = {o.y, o.z, o.w};
+    float y[3][RPL];
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) {
-      prod[j] = 1.0f;
-      any_true[j] = false;
+    for (int c = 0; c < 3; ++c) load_row<RPL>(a.x + (int64_t)(codes[c] >> 1) * a.ldx + r0, y[c]);
+    combine<RPL, 3>(codes, y, nother, rec_first(hdr), prod, any_true);
+  } else {
+    const int4 e = ldc4(a.occx, q);
+    const int codes[7] = {o.y, o.z, o.w, e.x, e.y, e.z, e.w};
+    float y[7][RPL];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const bool use = c < nother;
-        prod[j] *= use ? lit_factor(codes[c], y[k][c][j]) : 1.0f;
-        any_true[j] = any_true[j] || (use && lit_true(codes[c], y[k][c][j]));
+    for (int c = 0; c < 7; ++c) load_row<RPL>(a.x + (int64_t)(codes[c] >> 1) * a.ldx + r0, y[c]);
+    combine<RPL, 7>(codes, y, nother, rec_first(hdr), prod, any_true);
+  }
+  add_occurrence<RPL>(rec_neg(hdr), rec_first(hdr), prod, any_true, xv, g, lsum, usum);
+}
+
+// One GENERAL occurrence: the clause's other literals four at a time.
+template <int RPL>
+__device__ __forceinline__ void general_one(const VarPassArgs& a, const int4 o, int r0,
+                                            const float (&xv)[RPL], double (&g)[RPL],
+                                            double (&lsum)[RPL], int (&usum)[RPL]) {
+  const int t = o.y, p = o.z;
+  const int cs = ldc(a.clause_ptr, t), ce = ldc(a.clause_ptr, t + 1);
+  const bool first = p == cs;
+  float prod[RPL];
+  bool any_true[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) { prod[j] = 1.0f; any_true[j] = false; }
+  for (int i = cs; i < ce; i += 4) {
+    int codes[4];
+    float y[4][RPL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      // positions past the clause read the clause's first literal again and
+      // are masked out below, like the own position
+      const int iu = i + u < ce ? i + u : cs;
+      codes[u] = ldc(a.clause_lits, iu);
+      load_row<RPL>(a.x + (int64_t)(codes[u] >> 1) * a.ldx + r0, y[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool use = i + u < ce && i + u != p;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        prod[j] *= use ? lit_factor(codes[u], y[u][j]) : 1.0f;
+        any_true[j] = any_true[j] || (use && lit_true(codes[u], y[u][j]));
       }
     }
-    add_occurrence<RPL>((hdr & 4) != 0, (hdr & 8) != 0, prod, any_true, xv, g, lsum, usum);
   }
+  add_occurrence<RPL>((ldc(a.clause_lits, p) & 1) != 0, first, prod, any_true, xv, g, lsum, usum);
 }
 
 // One occurrence of any kind.
 template <int RPL>
-__device__ __forceinline__ void one_occurrence(const VarPassArgs& a, const int4 o, int r0,
+__device__ __forceinline__ void one_occurrence(const VarPassArgs& a, const int4 o, int q, int r0,
                                                const float (&xv)[RPL], double (&g)[RPL],
                                                double (&lsum)[RPL], int (&usum)[RPL]) {
   const int kind = rec_kind(o.x);
@@ -190,68 +286,44 @@ __device__ __forceinline__ void one_occurrence(const VarPassArgs& a, const int4 
     load_row<RPL>(a.D + (int64_t)o.y * a.ldD + r0, d);
 #pragma unroll
     for (int j = 0; j < RPL; ++j) g[j] += (double)d[j];
-    return;
-  }
-  float prod[RPL];
-  bool any_true[RPL];
-#pragma unroll
-  for (int j = 0; j < RPL; ++j) { prod[j] = 1.0f; any_true[j] = false; }
-  bool own_neg, first;
-  if (kind == kRecShort) {
-    const int nother = o.x & 3;
-    const int codes[3] = {o.y, o.z, o.w};
-    for (int c = 0; c < nother; ++c) {
-      float y[RPL];
-      load_row<RPL>(a.x + (int64_t)(codes[c] >> 1) * a.ldx + r0, y);
-#pragma unroll
-      for (int j = 0; j < RPL; ++j) {
-        prod[j] *= lit_factor(codes[c], y[j]);
-        any_true[j] = any_true[j] || lit_true(codes[c], y[j]);
-      }
-    }
-    own_neg = (o.x & 4) != 0;
-    first = (o.x & 8) != 0;
+  } else if (kind == kRecInline) {
+    inline_one<RPL>(a, o, q, r0, xv, g, lsum, usum);
   } else {
-    const int t = o.y, p = o.z;
-    const int cs = a.clause_ptr[t], ce = a.clause_ptr[t + 1];
-    for (int i = cs; i < ce; ++i) {
-      if (i == p) continue;
-      const int code = a.clause_lits[i];
-      float y[RPL];
-      load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + r0, y);
-#pragma unroll
-      for (int j = 0; j < RPL; ++j) {
-        prod[j] *= lit_factor(code, y[j]);
-        any_true[j] = any_true[j] || lit_true(code, y[j]);
-      }
-    }
-    own_neg = (a.clause_lits[p] & 1) != 0;
-    first = p == cs;
+    general_one<RPL>(a, o, r0, xv, g, lsum, usum);
   }
-  add_occurrence<RPL>(own_neg, first, prod, any_true, xv, g, lsum, usum);
 }
 
 // Adds the contributions of occurrences [q0, q1) (in that order) of the
-// variable whose own state is xv.  Inactive lanes (restarts >= R) skip all
-// row traffic.
+// variable whose own state is xv.  r0 must be a valid column for every lane
+// (lanes past the last restart pass a clamped one and discard the results),
+// so the loop runs under wave-uniform control and its table loads can be
+// scalar.
 template <int RPL>
-__device__ __forceinline__ void gather_occurrences(const VarPassArgs& a, int q0, int q1,
-                                                   bool active, int r0, const float (&xv)[RPL],
-                                                   double (&g)[RPL], double (&lsum)[RPL],
-                                                   int (&usum)[RPL]) {
-  if (!active) return;
+__device__ __forceinline__ void gather_occurrences(const VarPassArgs& a, int q0, int q1, int r0,
+                                                   const float (&xv)[RPL], double (&g)[RPL],
+                                                   double (&lsum)[RPL], int (&usum)[RPL]) {
   int q = q0;
   while (q < q1) {
     if (q + 4 <= q1) {
-      const int4 o[4] = {a.occ[q], a.occ[q + 1], a.occ[q + 2], a.occ[q + 3]};
-      const int kinds = rec_kind(o[0].x) | rec_kind(o[1].x) | rec_kind(o[2].x) | rec_kind(o[3].x);
-      if (kinds == kRecShort) {
-        short4<RPL>(a, o, r0, xv, g, lsum, usum);
+      const int4 o[4] = {ldc4(a.occ, q), ldc4(a.occ, q + 1), ldc4(a.occ, q + 2),
+                         ldc4(a.occ, q + 3)};
+      const int k0 = rec_kind(o[0].x), k1 = rec_kind(o[1].x), k2 = rec_kind(o[2].x),
+                k3 = rec_kind(o[3].x);
+      if ((k0 | k1 | k2 | k3) == kRecInline) {
+        const int most = max(max(rec_nother(o[0].x), rec_nother(o[1].x)),
+                             max(rec_nother(o[2].x), rec_nother(o[3].x)));
+        if (most <= 2) {
+          inline4<RPL, 2>(a, o, r0, xv, g, lsum, usum);
+        } else if (most <= 3) {
+          inline4<RPL, 3>(a, o, r0, xv, g, lsum, usum);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) inline_one<RPL>(a, o[k], q + k, r0, xv, g, lsum, usum);
+        }
         q += 4;
         continue;
       }
-      if (rec_kind(o[0].x) == kRecStored && rec_kind(o[1].x) == kRecStored &&
-          rec_kind(o[2].x) == kRecStored && rec_kind(o[3].x) == kRecStored) {
+      if (k0 == kRecStored && k1 == kRecStored && k2 == kRecStored && k3 == kRecStored) {
         float d[4][RPL];
 #pragma unroll
         for (int k = 0; k < 4; ++k) load_row<RPL>(a.D + (int64_t)o[k].y * a.ldD + r0, d[k]);
@@ -263,7 +335,7 @@ __device__ __forceinline__ void gather_occurrences(const VarPassArgs& a, int q0,
         continue;
       }
     }
-    one_occurrence<RPL>(a, a.occ[q], r0, xv, g, lsum, usum);
+    one_occurrence<RPL>(a, ldc4(a.occ, q), q, r0, xv, g, lsum, usum);
     ++q;
   }
 }
@@ -314,10 +386,14 @@ __global__ __launch_bounds__(kBlock) void k_var_pass(VarPassArgs a) {
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
   const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
-  const int chunk = a.chunk_base + blockIdx.x;
-  const int r0 = blockIdx.y * RT + lane * RPL;
+  const int chunk =
+      a.chunk_order ? ldc(a.chunk_order, a.chunk_base + blockIdx.x) : a.chunk_base + blockIdx.x;
+  if (chunk < 0) return;  // padding of the XCD-aware order: the whole block leaves
+  const int tile = a.tile_base + blockIdx.y;
+  const int r0 = tile * RT + lane * RPL;
   const bool active = r0 < a.R;
-  const int vb = a.chunk_vbeg[chunk], ve = a.chunk_vend[chunk];
+  const int rc = active ? r0 : 0;  // in-bounds column for lanes past the last restart
+  const int vb = ldc(a.chunk_vbeg, chunk), ve = ldc(a.chunk_vend, chunk);
   double lsum[RPL];
   int usum[RPL];
 #pragma unroll
@@ -328,12 +404,12 @@ __global__ __launch_bounds__(kBlock) void k_var_pass(VarPassArgs a) {
     double g[RPL];
     float xv[RPL];
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) { g[j] = 0.0; xv[j] = 0.0f; }
-    if (active) load_row<RPL>(a.x + (int64_t)v * a.ldx + r0, xv);
-    gather_occurrences<RPL>(a, a.var_ptr[v], a.var_ptr[v + 1], active, r0, xv, g, lsum, usum);
+    for (int j = 0; j < RPL; ++j) g[j] = 0.0;
+    load_row<RPL>(a.x + (int64_t)v * a.ldx + rc, xv);
+    gather_occurrences<RPL>(a, ldc(a.var_ptr, v), ldc(a.var_ptr, v + 1), rc, xv, g, lsum, usum);
     if (active) var_epilogue<RPL, MODE>(a, v, r0, xv, g);
   }
-  block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], a.R, a.loss_part, a.unsat_part);
+  block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], tile, a.R, a.loss_part, a.unsat_part);
 }
 
 // Segments of split variables (variables with more occurrences than one
@@ -345,9 +421,11 @@ __global__ __launch_bounds__(kBlock) void k_var_seg(VarPassArgs a) {
   constexpr int RT = LPI * RPL;
   const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
   const int chunk = a.chunk_base + blockIdx.x;
-  const int r0 = blockIdx.y * RT + lane * RPL;
+  const int tile = a.tile_base + blockIdx.y;
+  const int r0 = tile * RT + lane * RPL;
   const bool active = r0 < a.R;
-  const int sb = a.chunk_vbeg[chunk], se = a.chunk_vend[chunk];
+  const int rc = active ? r0 : 0;
+  const int sb = ldc(a.chunk_vbeg, chunk), se = ldc(a.chunk_vend, chunk);
   double lsum[RPL];
   int usum[RPL];
 #pragma unroll
@@ -355,19 +433,19 @@ __global__ __launch_bounds__(kBlock) void k_var_seg(VarPassArgs a) {
 
   for (int s0 = sb + slot; s0 < se; s0 += IPB) {
     const int sgi = uniform<LPI>(s0);
-    const int v = a.seg_var[sgi];
+    const int v = ldc(a.seg_var, sgi);
     double g[RPL];
     float xv[RPL];
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) { g[j] = 0.0; xv[j] = 0.0f; }
-    if (active) load_row<RPL>(a.x + (int64_t)v * a.ldx + r0, xv);
-    gather_occurrences<RPL>(a, a.seg_q0[sgi], a.seg_q1[sgi], active, r0, xv, g, lsum, usum);
+    for (int j = 0; j < RPL; ++j) g[j] = 0.0;
+    load_row<RPL>(a.x + (int64_t)v * a.ldx + rc, xv);
+    gather_occurrences<RPL>(a, ldc(a.seg_q0, sgi), ldc(a.seg_q1, sgi), rc, xv, g, lsum, usum);
     if (active) {
 #pragma unroll
       for (int j = 0; j < RPL; ++j) a.gseg[(int64_t)sgi * a.R + r0 + j] = g[j];
     }
   }
-  block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], a.R, a.loss_part, a.unsat_part);
+  block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], tile, a.R, a.loss_part, a.unsat_part);
 }
 
 // Split variables: their segments' partial gradients summed in segment
@@ -377,7 +455,8 @@ __global__ __launch_bounds__(kBlock) void k_heavy_finish(VarPassArgs a, int h0, 
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
   const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
-  const int r0 = blockIdx.y * RT + lane * RPL;
+  const int tile = a.tile_base + blockIdx.y;
+  const int r0 = tile * RT + lane * RPL;
   if (r0 >= a.R) return;
   for (int i = h0 + blockIdx.x * IPB + slot; i < h1; i += gridDim.x * IPB) {
     const int v = a.heavy_var[i];
@@ -407,61 +486,107 @@ __global__ __launch_bounds__(kBlock) void k_clause_pass(ClausePassArgs a) {
   constexpr int RT = LPI * RPL;
   const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
   const int chunk = a.chunk_base + blockIdx.x;
-  const int r0 = blockIdx.y * RT + lane * RPL;
+  const int tile = a.tile_base + blockIdx.y;
+  const int r0 = tile * RT + lane * RPL;
   const bool active = r0 < a.R;
-  const int cb = a.chunk_cbeg[chunk], ce = a.chunk_cend[chunk];
+  const int rc = active ? r0 : 0;  // in-bounds column for lanes past the last restart
+  const int cb = ldc(a.chunk_cbeg, chunk), ce = ldc(a.chunk_cend, chunk);
   double lsum[RPL];
   int usum[RPL];
 #pragma unroll
   for (int j = 0; j < RPL; ++j) { lsum[j] = 0.0; usum[j] = 0; }
 
   for (int c0 = cb + slot; c0 < ce; c0 += IPB) {
-    const int t = uniform<LPI>(a.clause_ids ? a.clause_ids[c0] : c0);
-    const int s = a.clause_ptr[t], e = a.clause_ptr[t + 1];
+    const int t = uniform<LPI>(a.clause_ids ? ldc(a.clause_ids, c0) : c0);
+    const int s = ldc(a.clause_ptr, t), e = ldc(a.clause_ptr, t + 1);
     float pre[RPL];
     bool any_true[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; ++j) { pre[j] = 1.0f; any_true[j] = false; }
-    for (int i = s; i < e; ++i) {
-      const int code = a.clause_lits[i];
-      if (active) {
-        float y[RPL];
-        load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + r0, y);
-        if constexpr (WRITE_D) store_row<RPL>(a.D + (int64_t)a.lit_dslot[i] * a.ldD + r0, pre);
+    // forward sweep, four literals' rows in flight at a time; with WRITE_D
+    // the prefix product before each literal is stored in its partial row
+    int i = s;
+    for (; i + 4 <= e; i += 4) {
+      int code[4];
+      float y[4][RPL];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) code[u] = ldc(a.clause_lits, i + u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) load_row<RPL>(a.x + (int64_t)(code[u] >> 1) * a.ldx + rc, y[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if constexpr (WRITE_D) {
+          if (active) store_row<RPL>(a.D + (int64_t)ldc(a.lit_dslot, i + u) * a.ldD + r0, pre);
+        }
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
-          pre[j] *= lit_factor(code, y[j]);
-          any_true[j] = any_true[j] || lit_true(code, y[j]);
+          pre[j] *= lit_factor(code[u], y[u][j]);
+          any_true[j] = any_true[j] || lit_true(code[u], y[u][j]);
         }
       }
     }
-    if (!active) continue;
+    for (; i < e; ++i) {
+      const int code = ldc(a.clause_lits, i);
+      float y[RPL];
+      load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + rc, y);
+      if constexpr (WRITE_D) {
+        if (active) store_row<RPL>(a.D + (int64_t)ldc(a.lit_dslot, i) * a.ldD + r0, pre);
+      }
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        pre[j] *= lit_factor(code, y[j]);
+        any_true[j] = any_true[j] || lit_true(code, y[j]);
+      }
+    }
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
       lsum[j] += (double)pre[j];
       usum[j] += any_true[j] ? 0 : 1;
     }
     if constexpr (WRITE_D) {
+      // backward sweep: partial = slope * prefix * suffix
       float suf[RPL];
 #pragma unroll
       for (int j = 0; j < RPL; ++j) suf[j] = 1.0f;
-      for (int i = e - 1; i >= s; --i) {
-        const int code = a.clause_lits[i];
+      int i2 = e - 1;
+      for (; i2 - 3 >= s; i2 -= 4) {
+        int code[4];
+        float y[4][RPL], d[4][RPL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) code[u] = ldc(a.clause_lits, i2 - u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          load_row<RPL>(a.x + (int64_t)(code[u] >> 1) * a.ldx + rc, y[u]);
+          load_row<RPL>(a.D + (int64_t)ldc(a.lit_dslot, i2 - u) * a.ldD + rc, d[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float slope = (code[u] & 1) ? 1.0f : -1.0f;
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) {
+            d[u][j] = slope * (d[u][j] * suf[j]);
+            suf[j] *= lit_factor(code[u], y[u][j]);
+          }
+          if (active) store_row<RPL>(a.D + (int64_t)ldc(a.lit_dslot, i2 - u) * a.ldD + r0, d[u]);
+        }
+      }
+      for (; i2 >= s; --i2) {
+        const int code = ldc(a.clause_lits, i2);
         float y[RPL], d[RPL];
-        load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + r0, y);
-        float* dp = a.D + (int64_t)a.lit_dslot[i] * a.ldD + r0;
-        load_row<RPL>(dp, d);
+        load_row<RPL>(a.x + (int64_t)(code >> 1) * a.ldx + rc, y);
+        float* dp = a.D + (int64_t)ldc(a.lit_dslot, i2) * a.ldD;
+        load_row<RPL>(dp + rc, d);
         const float slope = (code & 1) ? 1.0f : -1.0f;
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
           d[j] = slope * (d[j] * suf[j]);
           suf[j] *= lit_factor(code, y[j]);
         }
-        store_row<RPL>(dp, d);
+        if (active) store_row<RPL>(dp + r0, d);
       }
     }
   }
-  block_partials<LPI, RPL>(lsum, usum, a.chunk_row ? a.chunk_row[chunk] : chunk, a.R,
+  block_partials<LPI, RPL>(lsum, usum, a.chunk_row ? ldc(a.chunk_row, chunk) : chunk, tile, a.R,
                            a.loss_part, a.unsat_part);
 }
 
@@ -469,7 +594,10 @@ __global__ __launch_bounds__(kBlock) void k_clause_pass(ClausePassArgs a) {
 //
 // loss[f][r] = sum of the formula's partial rows (fixed order) + empty
 // clauses; the same for the unsat count.
-__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a) {
+// W waves per block: wave w sums rows w, w + W, ... for 64 restarts, then
+// the W partial sums are combined pairwise in a fixed tree.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_finalize(FinalizeArgs a) {
   const int f = a.f_base + blockIdx.x;
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int r = blockIdx.y * 64 + lane;
@@ -477,20 +605,28 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a) {
   double acc = 0.0;
   int uacc = 0;
   if (r < R) {
-    for (int row = a.a_beg[f] + w; row < a.a_end[f]; row += 4) {
+    const int rb = a.a_beg[f], re = a.a_end[f];
+    for (int row = rb + w; row < re; row += W) {
       if (a.loss_out) acc += a.loss_part[(int64_t)row * R + r];
       if (a.unsat_out) uacc += a.unsat_part[(int64_t)row * R + r];
     }
   }
-  __shared__ double sl[256];
-  __shared__ int su[256];
+  __shared__ double sl[64 * W];
+  __shared__ int su[64 * W];
   sl[threadIdx.x] = acc;
   su[threadIdx.x] = uacc;
   __syncthreads();
+#pragma unroll
+  for (int half = W / 2; half >= 1; half /= 2) {
+    if (w < half) {
+      sl[threadIdx.x] += sl[threadIdx.x + 64 * half];
+      su[threadIdx.x] += su[threadIdx.x + 64 * half];
+    }
+    __syncthreads();
+  }
   if (w == 0 && r < R) {
-    const double tot = ((sl[lane] + sl[64 + lane]) + (sl[128 + lane] + sl[192 + lane])) +
-                       (double)a.n_empty[f];
-    const int utot = su[lane] + su[64 + lane] + su[128 + lane] + su[192 + lane] + a.n_empty[f];
+    const double tot = sl[lane] + (double)a.n_empty[f];
+    const int utot = su[lane] + a.n_empty[f];
     if (a.loss_out) a.loss_out[(int64_t)f * R + r] = (float)tot;
     if (a.unsat_out) a.unsat_out[(int64_t)f * R + r] = utot;
   }
@@ -703,9 +839,16 @@ inline int grid_x_for(int64_t items_div4) {
 
 }  // namespace
 
+// Restart tiles of one launch: [tile_base, tile_base + tile_count), or all.
+template <class Args>
+inline int launch_tiles(const Args& a, Tile t) {
+  const int all = (a.R + t.tile() - 1) / t.tile() - a.tile_base;
+  return a.tile_count > 0 && a.tile_count < all ? a.tile_count : all;
+}
+
 hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
-  const int tiles = (a.R + t.tile() - 1) / t.tile();
+  const int tiles = launch_tiles(a, t);
   switch (t.lpi) {
     case 4: return var_pass_lpi<4>(a, mode, t, chunks, tiles, s);
     case 8: return var_pass_lpi<8>(a, mode, t, chunks, tiles, s);
@@ -717,7 +860,7 @@ hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, h
 
 hipError_t launch_var_seg(const VarPassArgs& a, Tile t, int chunks, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
-  const int tiles = (a.R + t.tile() - 1) / t.tile();
+  const int tiles = launch_tiles(a, t);
   switch (t.lpi) {
     case 4: return var_seg_lpi<4>(a, t, chunks, tiles, s);
     case 8: return var_seg_lpi<8>(a, t, chunks, tiles, s);
@@ -730,7 +873,7 @@ hipError_t launch_var_seg(const VarPassArgs& a, Tile t, int chunks, hipStream_t 
 hipError_t launch_heavy_finish(const VarPassArgs& a, int mode, Tile t, int h0, int h1,
                                hipStream_t s) {
   if (h1 <= h0) return hipSuccess;
-  const int tiles = (a.R + t.tile() - 1) / t.tile();
+  const int tiles = launch_tiles(a, t);
   switch (t.lpi) {
     case 4: return heavy_lpi<4>(a, mode, t, h0, h1, tiles, s);
     case 8: return heavy_lpi<8>(a, mode, t, h0, h1, tiles, s);
@@ -743,7 +886,7 @@ hipError_t launch_heavy_finish(const VarPassArgs& a, int mode, Tile t, int h0, i
 hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int chunks,
                               hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
-  const int tiles = (a.R + t.tile() - 1) / t.tile();
+  const int tiles = launch_tiles(a, t);
   switch (t.lpi) {
     case 4: return clause_pass_lpi<4>(a, write_d, t, chunks, tiles, s);
     case 8: return clause_pass_lpi<8>(a, write_d, t, chunks, tiles, s);
@@ -755,8 +898,12 @@ hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int
 
 hipError_t launch_finalize(const FinalizeArgs& a, int F, hipStream_t s) {
   if (F <= 0) return hipSuccess;
-  dim3 grid(F, (a.R + 63) / 64), block(256);
-  hipLaunchKernelGGL(k_finalize, grid, block, 0, s, a);
+  dim3 grid(F, (a.R + 63) / 64);
+  // few large formulas: more waves per formula; many small ones: fewer
+  if ((int64_t)F * grid.y < 256)
+    hipLaunchKernelGGL((k_finalize<16>), grid, dim3(1024), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_finalize<4>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

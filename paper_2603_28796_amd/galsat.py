@@ -76,7 +76,8 @@ class _Info(ctypes.Structure):
 
 # every symbol include/galsat.h declares
 EXPORTS = ("galsat_default_options", "galsat_create", "galsat_destroy", "galsat_init_state",
-           "galsat_loss_grad", "galsat_step", "galsat_round_check", "galsat_set_adam_step",
+           "galsat_loss_grad", "galsat_step", "galsat_step_prepare", "galsat_round_check",
+           "galsat_set_adam_step",
            "galsat_get_info", "galsat_profile", "galsat_kernel_times", "galsat_status_string",
            "galsat_last_error")
 
@@ -114,6 +115,7 @@ def load_library(path: Optional[str] = None):
     lib.galsat_init_state.argtypes = [_P, _P, _I32, ctypes.c_uint64, _P]
     lib.galsat_loss_grad.argtypes = [_P, _P, _I32, _P, _P, _P, _P]
     lib.galsat_step.argtypes = [_P, _P, _I32, _P, _I32, _P, _P, _P]
+    lib.galsat_step_prepare.argtypes = [_P, _P, _I32, _P, _I32, _P, _P]
     lib.galsat_round_check.argtypes = [_P, _P, _I32, _P, _P, _P, _P]
     lib.galsat_set_adam_step.argtypes = [_P, _I32]
     lib.galsat_get_info.argtypes = [_P, ctypes.POINTER(_Info)]
@@ -124,7 +126,8 @@ def load_library(path: Optional[str] = None):
     lib.galsat_last_error.argtypes = [_P]
     lib.galsat_last_error.restype = ctypes.c_char_p
     for fn in ("galsat_create", "galsat_destroy", "galsat_init_state", "galsat_loss_grad",
-               "galsat_step", "galsat_round_check", "galsat_set_adam_step", "galsat_get_info",
+               "galsat_step", "galsat_step_prepare", "galsat_round_check", "galsat_set_adam_step",
+               "galsat_get_info",
                "galsat_profile", "galsat_kernel_times"):
         getattr(lib, fn).restype = ctypes.c_int
     if path is None:
@@ -268,6 +271,14 @@ class Problem:
                                           _ptr(loss_trace), _ptr(unsat_trace), _stream()),
                     "galsat_step")
         return (loss_trace, unsat_trace) if trace else None
+
+    def prepare(self, x: torch.Tensor, steps: int, loss_trace: Optional[torch.Tensor] = None,
+                unsat_trace: Optional[torch.Tensor] = None):
+        """Capture the graph of step(x, steps, ...) without running it."""
+        ld = _state_ld(x, self.n, self.R)
+        self._check(self._lib.galsat_step_prepare(self._h, _ptr(x), ld, None, int(steps),
+                                                  _ptr(loss_trace), _ptr(unsat_trace)),
+                    "galsat_step_prepare")
 
     def round_check(self, x: torch.Tensor, want_assign: bool = True):
         """Returns (unsat [F, R] int32, best_restart [F] int32, assignment [n] uint8)."""

@@ -265,3 +265,26 @@ def test_round_check_ties_and_exact_points():
     check_counts(unsat, ref)
     assert int(unsat[0, 3]) == 0
     assert int(best[0]) == int(oracle.best(ref)[0])
+
+
+def test_graph_replay_matches_eager():
+    """galsat_step replayed from a captured graph, with eager work and
+    synchronisation between replays, equals eager execution every time."""
+    say("[graph]")
+    cnf = CASES["mixed20k"]()
+    R = 32
+    eager = Problem(cnf, R, partials="auto")
+    graph = Problem(cnf, R, partials="auto", use_graph=True)
+    x0 = _x0(cnf.n, R, 91)
+    xe, xg = x0.clone(), x0.clone()
+    lt_e = torch.empty((3, cnf.F, R), device="cuda")
+    ut_e = torch.empty((3, cnf.F, R), dtype=torch.int32, device="cuda")
+    lt_g, ut_g = torch.empty_like(lt_e), torch.empty_like(ut_e)
+    for rep in range(4):
+        eager.step(xe, 3, loss_trace=lt_e, unsat_trace=ut_e, trace=True)
+        graph.step(xg, 3, loss_trace=lt_g, unsat_trace=ut_g, trace=True)
+        junk = (xe * 2).sum()  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(xe, xg), f"replay {rep}: state differs"
+        assert torch.equal(lt_e, lt_g) and torch.equal(ut_e, ut_g), f"replay {rep}: traces differ"
+        del junk

@@ -137,8 +137,8 @@ def test_mixed_n1e6_recompute():
 @pytest.mark.timeout(300)
 def test_batch4096_general_vs_plain_and_oracle():
     """4,096 uneven formulas, R=32: the batched general schedule against the
-    oracle on sampled formulas, and bitwise against the one-formula-at-a-time
-    schedule."""
+    oracle on sampled formulas, and against the one-formula-at-a-time
+    schedule (bitwise for states and counts)."""
     w = I.WORKLOADS["batch4096"]
     cnf = workload(w.key)
     R = w.restarts
@@ -162,9 +162,11 @@ def test_batch4096_general_vs_plain_and_oracle():
     la, ua = prob.step(xa, 2, trace=True)
     lb, ub = plain.step(xb, 2, trace=True)
     torch.cuda.synchronize()
+    # same gradient sums in the same order: identical states and counts; the
+    # loss partial sums are grouped by chunk, which differs between plans
     assert torch.equal(xa, xb)
     assert torch.equal(ua, ub)
-    assert torch.equal(la, lb)
+    assert torch.allclose(la, lb, rtol=1e-6, atol=0)
 
 
 @pytest.mark.timeout(600)
