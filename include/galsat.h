@@ -191,6 +191,38 @@ galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, float* opt_sta
 galsat_status galsat_step_prepare(galsat_handle h, float* x, int32_t ldx, float* opt_state,
                                   int32_t steps, float* loss_trace, int32_t* unsat_trace);
 
+/* Straight-through Gumbel-softmax training, the paper's own optimizer loop
+ * (Section 3.2, Eq. 3-5; appendix "Experiment Setup": Adam, lr 0.5,
+ * tau 1.0).  Each (variable, restart) has two logits theta0, theta1; with
+ * two states the softmax of Eq. (3) depends only on d = theta1 - theta0 and
+ * on the noise difference l = g1 - g0 (g_j i.i.d. Gumbel(0,1)):
+ *   y1 = sigma((d + l) / tau),   forward at x_hat = [d + l > 0]   (Eq. 4,
+ *   a tie goes to state 0, taken in FP32),
+ * loss' and the unsat count are evaluated at x_hat (both equal the number
+ * of unsatisfied clauses there), and the straight-through backward sends
+ * g1 = G * y1 (1 - y1) / tau to theta1 and -g1 to theta0, G being the
+ * polynomial gradient at x_hat.  The handle's optimizer updates theta1 and
+ * theta0 with these gradients; the state kept is d, which moves by twice
+ * theta1's step (SGD: d -= 2 lr g1; Adam: theta0's moments are the exact
+ * negatives of theta1's, so opt_state [2][n][ldd] holds theta1's m and v).
+ * No clamp.  Noise for global step t (= step0 + k) is drawn from a
+ * counter-based generator:
+ *   g_j = -log(-log(u_j)), u_j = ((h_j >> 40) + 0.5) * 2^-24,
+ *   h_j = M(seed ^ M(c_j ^ M(t + 0x632be59bd9b4e019))), c_j = v * 2^32 + 2r + j,
+ * M the SplitMix64 output mix, evaluated in FP64 and rounded to FP32 once;
+ * or, when `noise` is not NULL, read from it ([steps][n][ldd] FP32 l values).
+ *   d            device FP32 [n][ldd], updated in place
+ *   loss_trace   device FP32 [steps][F*R] or NULL; unsat_trace int32, same */
+galsat_status galsat_gumbel_step(galsat_handle h, float* d, int32_t ldd, float* opt_state,
+                                 uint64_t seed, int32_t step0, int32_t steps, float tau,
+                                 const float* noise, float* loss_trace, int32_t* unsat_trace,
+                                 void* stream);
+
+/* The noise differences l of global step `step` that galsat_gumbel_step
+ * draws: device FP32 [n][ldn], r < R written. */
+galsat_status galsat_gumbel_noise(galsat_handle h, uint64_t seed, int32_t step, float* noise,
+                                  int32_t ldn, void* stream);
+
 /* Rounds x (x > 0.5 -> 1; an x that is already 0/1 is used as given),
  * counts unsatisfied clauses exactly per (formula, restart) with wavefront
  * ballot and popcount, and picks per formula the restart with the fewest
@@ -249,6 +281,24 @@ typedef struct {
 
 galsat_status galsat_profile(galsat_handle h, int32_t enable);
 galsat_status galsat_kernel_times(galsat_handle h, galsat_kernel_stats* out);
+
+/* Clause normalization to a fixed width (Section 3.2, "Clause Normalization
+ * for Vectorization", Eq. 6-7), host code, no device involved.
+ * A clause longer than `width` (>= 3) becomes a chain of width-literal
+ * clauses linked by fresh auxiliary variables: the first link holds the
+ * first width-1 literals and f1, each middle link ~f_i, width-2 literals and
+ * f_{i+1}, the last link ~f_last and the remaining literals; for width 3
+ * this is Eq. (6).  Shorter clauses (and a short last link) are padded by
+ * repeating their last literal; empty clauses stay empty.  Auxiliary
+ * variables get ids n_vars, n_vars+1, ... in order of creation, so original
+ * variables keep theirs.  Inputs: host int32 clause-major CSR
+ * (clause_ptr [n_clauses+1], clause_lits, codes 2*v+neg).  Call once with
+ * out_clause_ptr / out_clause_lits NULL to get the output sizes, then again
+ * with host buffers of [out_n_clauses+1] and [out_n_lits] entries. */
+galsat_status galsat_tseitin(int32_t width, int32_t n_vars, int32_t n_clauses,
+                             const int32_t* clause_ptr, const int32_t* clause_lits,
+                             int32_t* out_n_vars, int32_t* out_n_clauses, int32_t* out_n_lits,
+                             int32_t* out_clause_ptr, int32_t* out_clause_lits);
 
 /* Static description of a status code. */
 const char* galsat_status_string(galsat_status s);

@@ -54,9 +54,13 @@ def _L():
         lib.oracle_full_step.argtypes = [i32, i32, P, P, P, i32, f64, P, P, P, P]
         lib.oracle_init_state.argtypes = [u64, i32, i32, P]
         lib.oracle_splitmix64.argtypes = [u64, i32, P]
+        lib.oracle_gumbel_noise.argtypes = [u64, i32, i32, i32, P]
+        lib.oracle_gumbel_step.argtypes = [i32, i32, P, P, P, i32, P, P, f64, f64, f64, f64, f64,
+                                           i32, i32, P, P, P, P, P]
         for fn in ("oracle_loss", "oracle_grad", "oracle_grad_def", "oracle_fd_grad",
                    "oracle_step_sgd", "oracle_step_adam", "oracle_unsat", "oracle_best",
-                   "oracle_full_step", "oracle_init_state", "oracle_splitmix64"):
+                   "oracle_full_step", "oracle_init_state", "oracle_splitmix64",
+                   "oracle_gumbel_noise", "oracle_gumbel_step"):
             getattr(lib, fn).restype = None
         _lib = lib
     return _lib
@@ -223,3 +227,30 @@ def splitmix64(state: int, count: int) -> np.ndarray:
     out = np.empty(count, dtype=np.uint64)
     _L().oracle_splitmix64(ctypes.c_uint64(state), count, _p(out))
     return out
+
+
+def gumbel_noise(seed: int, t: int, n: int, R: int) -> np.ndarray:
+    """Noise differences g1 - g0 of step t, [R, n], FP64."""
+    out = np.empty((R, n), dtype=np.float64)
+    _L().oracle_gumbel_noise(ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), t, n, R, _p(out))
+    return out
+
+
+def gumbel_step(cnf, d, noise, tau: float = 1.0, lr: float = 0.5, b1: float = 0.9,
+                b2: float = 0.999, eps: float = 1e-8, t: int = 1, adam: bool = True, mom=None,
+                vel=None):
+    """One straight-through Gumbel step.  d, noise: [R, n] (noise is used as
+    FP32).  Returns dict(d, mom, vel, xh, loss [F,R], unsat [F,R])."""
+    n, F, fcb, cp, cl = _csr(cnf)
+    d = np.array(_x(d, n), copy=True)
+    R = d.shape[0]
+    l32 = np.ascontiguousarray(noise, dtype=np.float32)
+    assert l32.shape == d.shape
+    mom = np.zeros_like(d) if mom is None else np.array(mom, dtype=np.float64, copy=True)
+    vel = np.zeros_like(d) if vel is None else np.array(vel, dtype=np.float64, copy=True)
+    xh = np.empty_like(d)
+    lo = np.empty((F, R), dtype=np.float64)
+    us = np.empty((F, R), dtype=np.int32)
+    _L().oracle_gumbel_step(n, F, _p(fcb), _p(cp), _p(cl), R, _p(d), _p(l32), tau, lr, b1, b2, eps,
+                            t, 1 if adam else 0, _p(mom), _p(vel), _p(xh), _p(lo), _p(us))
+    return {"d": d, "mom": mom, "vel": vel, "xh": xh, "loss": lo, "unsat": us}

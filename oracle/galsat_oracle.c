@@ -306,3 +306,71 @@ void oracle_init_state(uint64_t seed, int32_t n, int32_t R, double* x) {
       x[(int64_t)r * n + v] = (double)(h >> 40) * (1.0 / 16777216.0);
     }
 }
+
+/* ---- Straight-through Gumbel-softmax mode (Section 3.2, Eq. 3-5) ----
+ *
+ * Two logits per (variable, restart) enter a temperature softmax after
+ * i.i.d. Gumbel(0,1) noise (Eq. 3); the forward uses the hard argmax
+ * (Eq. 4) and the backward substitutes the soft probabilities' gradient.
+ * With two states the softmax depends only on the logit difference
+ * d = theta1 - theta0 and the noise difference l = g1 - g0:
+ *   y1 = sigma((d + l) / tau),   x_hat = [d + l > 0]   (tie -> state 0).
+ * The gradient reaching theta1 is G * y1 * (1 - y1) / tau, with G the
+ * gradient of loss' at x_hat, and theta0 receives its negative. */
+
+/* Gumbel noise difference for step t: l = g1 - g0 with
+ *   g_j = -log(-log(u_j)),  u_j = ((h_j >> 40) + 0.5) * 2^-24,
+ *   h_j = mix(seed ^ mix(c_j ^ mix(t + 0x632be59bd9b4e019))),
+ *   c_j = v * 2^32 + 2 r + j,
+ * mix being the SplitMix64 output mix.  out is [R][n]. */
+void oracle_gumbel_noise(uint64_t seed, int32_t t, int32_t n, int32_t R, double* out) {
+  const uint64_t ts = splitmix_mix((uint64_t)(uint32_t)t + 0x632be59bd9b4e019ULL);
+  for (int32_t r = 0; r < R; ++r)
+    for (int32_t v = 0; v < n; ++v) {
+      double g[2];
+      for (int j = 0; j < 2; ++j) {
+        const uint64_t c = ((uint64_t)(uint32_t)v << 32) + 2 * (uint64_t)(uint32_t)r + (uint64_t)j;
+        const uint64_t h = splitmix_mix(seed ^ splitmix_mix(c ^ ts));
+        const double u = ((double)(h >> 40) + 0.5) * (1.0 / 16777216.0);
+        g[j] = -log(-log(u));
+      }
+      out[(int64_t)r * n + v] = g[1] - g[0];
+    }
+}
+
+/* One straight-through Gumbel step on the logit differences d ([R][n]),
+ * given the noise differences l ([R][n], FP32 values).  The hard decision
+ * d + l > 0 is taken in FP32, as the kernels take it.  Writes loss' and the
+ * unsat count of x_hat ([F][R]; both equal the number of unsatisfied
+ * clauses), then updates d:
+ *   adam = 0:  theta1 -= lr * g1, theta0 += lr * g1, so d -= 2 lr g1;
+ *   adam = 1:  Adam on theta1 with gradient g1 (theta0's moments are the
+ *              exact negatives, its step the negative), so d moves by twice
+ *              theta1's Adam step; t is the 1-based Adam step.
+ * mom/vel are theta1's moments ([R][n]); x_hat is returned in xh. */
+void oracle_gumbel_step(int32_t n, int32_t F, const int32_t* fcb, const int32_t* cptr,
+                        const int32_t* lits, int32_t R, double* d, const float* l, double tau,
+                        double lr, double b1, double b2, double eps, int32_t t, int32_t adam,
+                        double* mom, double* vel, double* xh, double* loss, int32_t* unsat) {
+  const int64_t cnt = (int64_t)R * n;
+  double* G = (double*)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
+  for (int64_t i = 0; i < cnt; ++i) {
+    const float s = (float)d[i] + l[i];
+    xh[i] = s > 0.0f ? 1.0 : 0.0;
+  }
+  oracle_grad(n, F, fcb, cptr, lits, R, xh, loss, G, NULL);
+  oracle_unsat(n, F, fcb, cptr, lits, R, xh, unsat);
+  const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+  for (int64_t i = 0; i < cnt; ++i) {
+    const double y1 = 1.0 / (1.0 + exp(-(d[i] + (double)l[i]) / tau));
+    const double g1 = G[i] * y1 * (1.0 - y1) / tau;
+    if (adam) {
+      mom[i] = b1 * mom[i] + (1.0 - b1) * g1;
+      vel[i] = b2 * vel[i] + (1.0 - b2) * g1 * g1;
+      d[i] -= 2.0 * lr * (mom[i] / c1) / (sqrt(vel[i] / c2) + eps);
+    } else {
+      d[i] -= 2.0 * lr * g1;
+    }
+  }
+  free(G);
+}

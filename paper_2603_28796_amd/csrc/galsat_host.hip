@@ -156,6 +156,7 @@ struct galsat_ctx {
   int32_t *f_vbeg = nullptr, *f_cbeg = nullptr;
   // workspace
   float *D = nullptr, *xa = nullptr, *xb = nullptr;
+  float* nbuf = nullptr;  // noise of the straight-through Gumbel mode (allocated on first use)
   double* loss_part = nullptr;
   double* gseg = nullptr;
   int32_t* unsat_part = nullptr;
@@ -334,8 +335,9 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
   return s;
 }
 
-// Parses "key=value,key=value" plan overrides: lpi, rpl, krec, tg.
-void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg) {
+// Parses "key=value,key=value" plan overrides: lpi, rpl, krec, tg, xcdc
+// (chunks per formula of multi-formula launches; 0 turns the XCD order off).
+void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -351,16 +353,21 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg) {
       else if (k == "rpl") *rpl = v;
       else if (k == "krec") *krec = v;
       else if (k == "tg") *tg = v;
+      else if (k == "xcdc") *xcdc = v;
     }
     pos = comma + 1;
   }
 }
 
+// Default lanes-per-item / restarts-per-lane.  Wide restart batches take 4
+// consecutive restarts per lane (one 16-byte load per lane, 1 KB per wave
+// and row); at 32 restarts or fewer one restart per lane measured faster
+// (two variables per wave instead of eight).
 Tile choose_tile(int R, int rpl_max) {
   Tile t;
   int rpl = 1;
-  if (rpl_max >= 4 && R % 4 == 0) rpl = 4;
-  else if (rpl_max >= 2 && R % 2 == 0) rpl = 2;
+  if (R > 32 && rpl_max >= 4 && R % 4 == 0) rpl = 4;
+  else if (R > 32 && rpl_max >= 2 && R % 2 == 0) rpl = 2;
   int per_lane = (R + rpl - 1) / rpl;
   int lpi = pow2_ceil(per_lane);
   lpi = std::max(4, std::min(64, lpi));
@@ -519,8 +526,9 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   (void)hipGetDevice(&h->device);
 
   // ---- plan: which clauses recompute their partials in the variable pass
-  int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0;
-  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o);
+  int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1;
+  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o);
+  const int64_t xcd_chunks = xcdc_o >= 0 ? xcdc_o : kXcdChunks;
   int32_t krec;
   if (opt.partials == GALSAT_PARTIALS_STORE) krec = -1;           // every clause stores
   else if (opt.partials == GALSAT_PARTIALS_RECOMPUTE) krec = kmax;
@@ -665,11 +673,11 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       fcost[f] = cost_f;
       if (per_formula) {
         target_f = std::max<int64_t>(64, cost_f / chunks_target);
-      } else if (F > 1) {
+      } else if (F > 1 && xcd_chunks > 0) {
         // many formulas in one launch: about kXcdChunks chunks per formula,
         // so the workgroups resident on one XCD work on one formula at a
         // time and its state stays in that XCD's L2 (see the launch order)
-        target_f = std::max<int64_t>(64, cost_f / kXcdChunks);
+        target_f = std::max<int64_t>(64, cost_f / xcd_chunks);
       }
       for (int32_t v = fvb[f]; v < fvb[f + 1]; ++v) {
         if (vcost[v] > item_cap_f && vp[v + 1] - vp[v] > 1) {
@@ -723,7 +731,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     // formulas are split into 8 groups of balanced cost (longest first) and
     // group x's chunks are placed at indices x, x + 8, x + 16, ...; padding
     // indices (-1) do nothing.
-    if (F > 1 && !per_formula) {
+    if (F > 1 && !per_formula && xcd_chunks > 0) {
       std::vector<int32_t> ford(F);
       for (int32_t f = 0; f < F; ++f) ford[f] = f;
       std::stable_sort(ford.begin(), ford.end(),
@@ -1225,6 +1233,68 @@ extern "C" galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, flo
     return GALSAT_OK;
   }
   return enqueue_steps(h, t, x, ldx, mom, vel, steps, loss_trace, unsat_trace, s);
+}
+
+extern "C" galsat_status galsat_gumbel_noise(galsat_handle h, uint64_t seed, int32_t step,
+                                             float* noise, int32_t ldn, void* stream) {
+  GS_CHECK_HANDLE(h);
+  if (!noise && h->n > 0) return h->fail(GALSAT_EINVAL, "noise is NULL");
+  if (ldn < h->R) return h->fail(GALSAT_EINVAL, "ldn < restarts");
+  GS_HIP(h, launch_gumbel_noise(noise, ldn, h->n, h->R, seed, step, static_cast<hipStream_t>(stream)),
+         "gumbel noise");
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_gumbel_step(galsat_handle h, float* d, int32_t ldd, float* opt_state,
+                                            uint64_t seed, int32_t step0, int32_t steps, float tau,
+                                            const float* noise, float* loss_trace,
+                                            int32_t* unsat_trace, void* stream) {
+  GS_CHECK_HANDLE(h);
+  if (!d && h->n > 0) return h->fail(GALSAT_EINVAL, "d is NULL");
+  if (ldd < h->R) return h->fail(GALSAT_EINVAL, "ldd < restarts");
+  if (steps < 0 || step0 < 0) return h->fail(GALSAT_EINVAL, "steps and step0 must be >= 0");
+  if (!(tau > 0.0f) || !std::isfinite(tau)) return h->fail(GALSAT_EINVAL, "tau must be > 0");
+  const bool adam = h->opt.optimizer == GALSAT_OPT_ADAM;
+  if (adam && !opt_state && h->n > 0) return h->fail(GALSAT_EINVAL, "Adam needs opt_state");
+  if (steps == 0) return GALSAT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the hard point, its gradient and the step's noise live in the internal
+  // state buffers (xa, xb) and one more buffer of the same shape
+  hipError_t he;
+  if (!h->nbuf && (he = h->alloc(&h->nbuf, (size_t)h->n * h->ld)) != hipSuccess)
+    return h->fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE, "noise buffer");
+  float* xh = h->xa;
+  float* gb = h->xb;
+  float* mom = adam ? opt_state : nullptr;
+  float* vel = adam ? opt_state + (int64_t)h->n * ldd : nullptr;
+  const int64_t FR = (int64_t)h->F * h->R;
+  for (int32_t k = 0; k < steps; ++k) {
+    const float* nk = noise ? noise + (int64_t)k * h->n * ldd : nullptr;
+    {
+      ProfScope _ps(h, GALSAT_K_COPY, s);
+      GS_HIP(h, launch_gumbel_prep(d, ldd, nk, ldd, seed, step0 + k, h->n, h->R, xh, h->nbuf, h->ld, s),
+             "gumbel prep");
+    }
+    galsat_status st = grad_passes(h, h->tile, kModeGrad, xh, h->ld, gb, h->ld, nullptr, nullptr, 0,
+                                   nullptr, 0, h->F, s);
+    if (st != GALSAT_OK) return st;
+    st = finalize_step(h, loss_trace ? loss_trace + k * FR : nullptr,
+                       unsat_trace ? unsat_trace + k * FR : nullptr, 0, h->F, s);
+    if (st != GALSAT_OK) return st;
+    double inv_c1 = 1.0, inv_c2 = 1.0;
+    if (adam) {
+      const int tt = h->adam_t + 1;
+      inv_c1 = 1.0 / (1.0 - std::pow((double)h->opt.beta1, tt));
+      inv_c2 = 1.0 / (1.0 - std::pow((double)h->opt.beta2, tt));
+      h->adam_t++;
+    }
+    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+    GS_HIP(h, launch_gumbel_update(d, ldd, h->nbuf, gb, h->ld, mom, vel, ldd, h->n, h->R, tau,
+                                   h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps, inv_c1, inv_c2,
+                                   adam ? 1 : 0, s),
+           "gumbel update");
+  }
+  return GALSAT_OK;
 }
 
 extern "C" galsat_status galsat_round_check(galsat_handle h, const float* x, int32_t ldx,

@@ -120,39 +120,15 @@ hipError_t launch_best(const int32_t* unsat, int32_t F, int32_t R, int32_t* best
 hipError_t launch_best_assign(const uint64_t* bits, int32_t n, const int32_t* var_formula,
                               const int32_t* best, uint8_t* out, hipStream_t s);
 
-// Batched schedule: one persistent launch, all steps in-kernel, each work
-// item's state in LDS (galsat_batched.hip).
-struct BatchedArgs {
-  const int32_t* item_formula;   // [items] in launch (LPT) order
-  const int32_t* item_r0;        // first restart of the item
-  const int32_t* item_rcount;    // restarts of the item
-  const int32_t* f_vbeg;         // [F+1]
-  const int32_t* f_cbeg;         // [F+1]
-  const int32_t* var_ptr;
-  const int32_t* var_occ;
-  const int32_t* occ_rec;        // clause id of every occurrence (all recompute)
-  const int32_t* clause_ptr;
-  const int32_t* clause_lits;
-  const int32_t* n_empty;        // [F]
-  float* x;                      // caller state [n][ldx], read at start, written at end
-  int32_t ldx;
-  float* mom;
-  float* vel;
-  int32_t ldm;
-  float* loss_trace;             // [steps][F*R] or null
-  int32_t* unsat_trace;
-  int32_t* work_counter;         // persistent work queue head (zeroed before launch)
-  int32_t items;
-  int32_t steps;
-  int32_t R;
-  int32_t F;
-  int32_t optimizer;
-  float lr, b1, b2, eps;
-  int32_t adam_t0;               // Adam step counter before the first step
-  int32_t lds_floats;            // LDS floats available for state
-};
-
-hipError_t launch_batched(const BatchedArgs& a, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_gumbel_noise(float* out, int32_t ldo, int32_t n, int32_t R, uint64_t seed,
+                               int32_t t, hipStream_t s);
+hipError_t launch_gumbel_prep(const float* d, int32_t ldd, const float* noise, int32_t ldn,
+                              uint64_t seed, int32_t t, int32_t n, int32_t R, float* xh, float* nb,
+                              int32_t ld, hipStream_t s);
+hipError_t launch_gumbel_update(float* d, int32_t ldd, const float* nb, const float* G, int32_t ld,
+                                float* mom, float* vel, int32_t ldm, int32_t n, int32_t R, float tau,
+                                float lr, float b1, float b2, float eps, double inv_c1,
+                                double inv_c2, int32_t adam, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s);
 
 }  // namespace galsat

@@ -666,6 +666,88 @@ __global__ void k_zero_i32(int32_t* p, int64_t count) {
     p[i] = 0;
 }
 
+// ------------------------------------------- straight-through Gumbel mode
+//
+// Two logits per (variable, restart) go through a temperature softmax after
+// Gumbel(0,1) noise (Section 3.2, Eq. 3); the forward uses the hard argmax
+// (Eq. 4) and the backward the soft probabilities.  With two states only the
+// logit difference d = theta1 - theta0 and the noise difference
+// l = g1 - g0 matter: y1 = sigma((d + l) / tau), x_hat = [d + l > 0].
+
+// Noise difference of step t for (v, r): g_j = -log(-log(u_j)) with
+// u_j = ((h_j >> 40) + 0.5) * 2^-24 and h_j the SplitMix64 mix of
+// (seed, v * 2^32 + 2r + j, t), evaluated in FP64 and rounded once.
+__device__ __forceinline__ float gumbel_diff(uint64_t seed, int t, int64_t v, int r) {
+  const uint64_t ts = splitmix_mix((uint64_t)(uint32_t)t + 0x632be59bd9b4e019ULL);
+  double g[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const uint64_t c = ((uint64_t)(uint32_t)v << 32) + 2 * (uint64_t)(uint32_t)r + (uint64_t)j;
+    const uint64_t h = splitmix_mix(seed ^ splitmix_mix(c ^ ts));
+    const double u = ((double)(h >> 40) + 0.5) * (1.0 / 16777216.0);
+    g[j] = -log(-log(u));
+  }
+  return (float)(g[1] - g[0]);
+}
+
+__global__ __launch_bounds__(256) void k_gumbel_noise(float* out, int32_t ldo, int32_t n, int32_t R,
+                                                      uint64_t seed, int32_t t) {
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int r = blockIdx.y * 64 + lane;
+  if (r >= R) return;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + w; v < n; v += (int64_t)gridDim.x * 4)
+    out[v * ldo + r] = gumbel_diff(seed, t, v, r);
+}
+
+// Hard point of the step: xh = [d + l > 0] (FP32 sum; a tie goes to state
+// 0), keeping l for the update.  noise: caller-given l or null to draw it.
+__global__ __launch_bounds__(256) void k_gumbel_prep(const float* d, int32_t ldd, const float* noise,
+                                                     int32_t ldn, uint64_t seed, int32_t t,
+                                                     int32_t n, int32_t R, float* xh, float* nb,
+                                                     int32_t ld) {
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int r = blockIdx.y * 64 + lane;
+  if (r >= R) return;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + w; v < n; v += (int64_t)gridDim.x * 4) {
+    const float l = noise ? noise[v * ldn + r] : gumbel_diff(seed, t, v, r);
+    const float s = d[v * ldd + r] + l;
+    xh[v * ld + r] = s > 0.0f ? 1.0f : 0.0f;
+    nb[v * ld + r] = l;
+  }
+}
+
+// Soft backward and update: g1 = G * y1 (1 - y1) / tau reaches theta1 and
+// -g1 reaches theta0, so d moves by twice theta1's step (SGD, or Adam whose
+// theta0 moments are the exact negatives of theta1's).
+__global__ __launch_bounds__(256) void k_gumbel_update(float* d, int32_t ldd, const float* nb,
+                                                       const float* G, int32_t ld, float* mom,
+                                                       float* vel, int32_t ldm, int32_t n,
+                                                       int32_t R, float tau, float lr, float b1,
+                                                       float b2, float eps, double inv_c1,
+                                                       double inv_c2, int32_t adam) {
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int r = blockIdx.y * 64 + lane;
+  if (r >= R) return;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + w; v < n; v += (int64_t)gridDim.x * 4) {
+    const double dv = d[v * ldd + r];
+    const double z = (dv + (double)nb[v * ld + r]) / (double)tau;
+    const double y1 = 1.0 / (1.0 + exp(-z));
+    const double g1 = (double)G[v * ld + r] * y1 * (1.0 - y1) / (double)tau;
+    double step;
+    if (adam) {
+      const double mm = (double)b1 * (double)mom[v * ldm + r] + (1.0 - (double)b1) * g1;
+      const double vv = (double)b2 * (double)vel[v * ldm + r] + (1.0 - (double)b2) * g1 * g1;
+      mom[v * ldm + r] = (float)mm;
+      vel[v * ldm + r] = (float)vv;
+      step = (double)lr * ((double)(float)mm * inv_c1) /
+             (sqrt((double)(float)vv * inv_c2) + (double)eps);
+    } else {
+      step = (double)lr * g1;
+    }
+    d[v * ldd + r] = (float)(dv - 2.0 * step);
+  }
+}
+
 // ------------------------------------------------------- round & count
 //
 // bits[w][v]: bit l = [x[v][64w + l] > 0.5] packed by one wavefront ballot.
@@ -946,6 +1028,34 @@ hipError_t launch_count_unsat(const int32_t* clause_ptr, const int32_t* clause_l
   dim3 grid(chunks, (R + 63) / 64), block(256);
   hipLaunchKernelGGL(k_count_unsat, grid, block, 0, s, clause_ptr, clause_lits, chunk_cbeg,
                      chunk_cend, bits, n, R, unsat_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_gumbel_noise(float* out, int32_t ldo, int32_t n, int32_t R, uint64_t seed,
+                               int32_t t, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(grid_x_for(((int64_t)n + 3) / 4), (R + 63) / 64), block(256);
+  hipLaunchKernelGGL(k_gumbel_noise, grid, block, 0, s, out, ldo, n, R, seed, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_gumbel_prep(const float* d, int32_t ldd, const float* noise, int32_t ldn,
+                              uint64_t seed, int32_t t, int32_t n, int32_t R, float* xh, float* nb,
+                              int32_t ld, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(grid_x_for(((int64_t)n + 3) / 4), (R + 63) / 64), block(256);
+  hipLaunchKernelGGL(k_gumbel_prep, grid, block, 0, s, d, ldd, noise, ldn, seed, t, n, R, xh, nb, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_gumbel_update(float* d, int32_t ldd, const float* nb, const float* G, int32_t ld,
+                                float* mom, float* vel, int32_t ldm, int32_t n, int32_t R, float tau,
+                                float lr, float b1, float b2, float eps, double inv_c1,
+                                double inv_c2, int32_t adam, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(grid_x_for(((int64_t)n + 3) / 4), (R + 63) / 64), block(256);
+  hipLaunchKernelGGL(k_gumbel_update, grid, block, 0, s, d, ldd, nb, G, ld, mom, vel, ldm, n, R, tau,
+                     lr, b1, b2, eps, inv_c1, inv_c2, adam);
   return hipGetLastError();
 }
 

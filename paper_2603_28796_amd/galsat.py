@@ -76,10 +76,11 @@ class _Info(ctypes.Structure):
 
 # every symbol include/galsat.h declares
 EXPORTS = ("galsat_default_options", "galsat_create", "galsat_destroy", "galsat_init_state",
-           "galsat_loss_grad", "galsat_step", "galsat_step_prepare", "galsat_round_check",
+           "galsat_loss_grad", "galsat_step", "galsat_step_prepare", "galsat_gumbel_step",
+           "galsat_gumbel_noise", "galsat_round_check",
            "galsat_set_adam_step",
-           "galsat_get_info", "galsat_profile", "galsat_kernel_times", "galsat_status_string",
-           "galsat_last_error")
+           "galsat_get_info", "galsat_profile", "galsat_kernel_times", "galsat_tseitin",
+           "galsat_status_string", "galsat_last_error")
 
 KERNEL_KINDS = ("var_pass", "clause_pass", "finalize", "copy", "pack", "count", "select",
                 "batched")
@@ -116,17 +117,23 @@ def load_library(path: Optional[str] = None):
     lib.galsat_loss_grad.argtypes = [_P, _P, _I32, _P, _P, _P, _P]
     lib.galsat_step.argtypes = [_P, _P, _I32, _P, _I32, _P, _P, _P]
     lib.galsat_step_prepare.argtypes = [_P, _P, _I32, _P, _I32, _P, _P]
+    lib.galsat_gumbel_step.argtypes = [_P, _P, _I32, _P, ctypes.c_uint64, _I32, _I32,
+                                       ctypes.c_float, _P, _P, _P, _P]
+    lib.galsat_gumbel_noise.argtypes = [_P, ctypes.c_uint64, _I32, _P, _I32, _P]
     lib.galsat_round_check.argtypes = [_P, _P, _I32, _P, _P, _P, _P]
     lib.galsat_set_adam_step.argtypes = [_P, _I32]
     lib.galsat_get_info.argtypes = [_P, ctypes.POINTER(_Info)]
     lib.galsat_profile.argtypes = [_P, _I32]
     lib.galsat_kernel_times.argtypes = [_P, ctypes.POINTER(_KernelTimes)]
+    lib.galsat_tseitin.argtypes = [_I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]
+    lib.galsat_tseitin.restype = ctypes.c_int
     lib.galsat_status_string.argtypes = [ctypes.c_int]
     lib.galsat_status_string.restype = ctypes.c_char_p
     lib.galsat_last_error.argtypes = [_P]
     lib.galsat_last_error.restype = ctypes.c_char_p
     for fn in ("galsat_create", "galsat_destroy", "galsat_init_state", "galsat_loss_grad",
-               "galsat_step", "galsat_step_prepare", "galsat_round_check", "galsat_set_adam_step",
+               "galsat_step", "galsat_step_prepare", "galsat_gumbel_step", "galsat_gumbel_noise",
+               "galsat_round_check", "galsat_set_adam_step",
                "galsat_get_info",
                "galsat_profile", "galsat_kernel_times"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -272,6 +279,34 @@ class Problem:
                     "galsat_step")
         return (loss_trace, unsat_trace) if trace else None
 
+    def gumbel_step(self, d: torch.Tensor, steps: int = 1, opt_state: Optional[torch.Tensor] = None,
+                    seed: int = 0, step0: int = 0, tau: float = 1.0,
+                    noise: Optional[torch.Tensor] = None, trace: bool = False):
+        """Straight-through Gumbel steps on the logit differences d [n, ld]
+        (in place).  With trace=True returns (loss_trace, unsat_trace)."""
+        ld = _state_ld(d, self.n, self.R, "d")
+        if self.optimizer == "adam" and opt_state is None:
+            raise ValueError("Adam needs opt_state (see new_opt_state)")
+        if noise is not None:
+            if noise.shape[-2:] != d.shape or not noise.is_contiguous() or d.stride(0) != d.shape[1]:
+                raise ValueError("noise must be a contiguous [steps, n, ld] tensor matching d")
+        lt = ut = None
+        if trace:
+            lt = torch.empty((steps, self.F, self.R), dtype=torch.float32, device=d.device)
+            ut = torch.empty((steps, self.F, self.R), dtype=torch.int32, device=d.device)
+        self._check(self._lib.galsat_gumbel_step(self._h, _ptr(d), ld, _ptr(opt_state),
+                                                 ctypes.c_uint64(seed), int(step0), int(steps),
+                                                 float(tau), _ptr(noise), _ptr(lt), _ptr(ut),
+                                                 _stream()), "galsat_gumbel_step")
+        return (lt, ut) if trace else None
+
+    def gumbel_noise(self, seed: int, step: int, ld: Optional[int] = None) -> torch.Tensor:
+        out = torch.zeros((self.n, ld or self.R), dtype=torch.float32, device="cuda")
+        self._check(self._lib.galsat_gumbel_noise(self._h, ctypes.c_uint64(seed), int(step),
+                                                  _ptr(out), out.shape[1], _stream()),
+                    "galsat_gumbel_noise")
+        return out
+
     def prepare(self, x: torch.Tensor, steps: int, loss_trace: Optional[torch.Tensor] = None,
                 unsat_trace: Optional[torch.Tensor] = None):
         """Capture the graph of step(x, steps, ...) without running it."""
@@ -310,6 +345,31 @@ class Problem:
         d = {k: getattr(inf, k) for k, _ in _Info._fields_}
         d["schedule"] = SCHEDULE_NAME.get(d["schedule"], d["schedule"])
         return d
+
+
+def tseitin(cnf, width: int = 3):
+    """Fixed-width chain normalization of a single formula (galsat_tseitin,
+    host code).  Returns a CNF with the auxiliary variables appended after
+    the original ones."""
+    from . import inputs as I
+
+    if cnf.F != 1:
+        raise ValueError("normalize one formula at a time (CNF.sub)")
+    lib = load_library()
+    cp = np.ascontiguousarray(cnf.clause_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(cnf.clause_lits, dtype=np.int32)
+    nv, nm, nl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    args = (int(width), cnf.n, cnf.m, cp.ctypes.data, cl.ctypes.data if cl.size else None,
+            ctypes.byref(nv), ctypes.byref(nm), ctypes.byref(nl))
+    st = lib.galsat_tseitin(*args, None, None)
+    if st != 0:
+        raise GalsatError(st, "galsat_tseitin", lib.galsat_status_string(st).decode())
+    ocp = np.empty(nm.value + 1, dtype=np.int32)
+    ocl = np.empty(max(nl.value, 1), dtype=np.int32)
+    st = lib.galsat_tseitin(*args, ocp.ctypes.data, ocl.ctypes.data)
+    if st != 0:
+        raise GalsatError(st, "galsat_tseitin", lib.galsat_status_string(st).decode())
+    return I.csr_from_clause_major(nv.value, ocp, ocl[:nl.value], name=f"{cnf.name}/w{width}")
 
 
 class GalsatLoss(torch.autograd.Function):

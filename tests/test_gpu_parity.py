@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_2603_28796_amd import inputs as I
-from paper_2603_28796_amd.galsat import Problem, GalsatLoss
+from paper_2603_28796_amd.galsat import Problem, GalsatLoss, tseitin
 from tests.gpu_util import (check_counts, check_grad, check_loss, check_update, parity_at, say,
                             to_oracle, from_oracle)
 
@@ -48,6 +48,8 @@ CASES = {
     "batch": _batch,
     "long_mix": lambda: I.generate(I.spec(2, k0=3, ka=50, kb=200, p0=0.9, var_kind=1, zipf_s=1.2),
                                    13, [5000], [6000], "long_mix"),
+    # the mixed-length instance after width-3 chain normalization (Eq. 6)
+    "tseitin3": lambda: tseitin(I.structured_mixed(n=4000, m=16000, n_comm=4, seed=14), 3),
 }
 
 

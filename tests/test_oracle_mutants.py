@@ -7,6 +7,7 @@ import os
 import pytest
 
 import oracle
+from tests import test_oracle_gumbel as Gp
 from tests import test_oracle_pins as P
 from tests.conftest import read_golden
 
@@ -20,7 +21,13 @@ MUTANTS = {
     "best_tie_last": ("if (unsat[(int64_t)f * R + r] < unsat[(int64_t)f * R + b]) b = r;",
                       "if (unsat[(int64_t)f * R + r] <= unsat[(int64_t)f * R + b]) b = r;"),
     "loss_transposed": ("if (loss) loss[(int64_t)f * R + r] = s;", "if (loss) loss[(int64_t)r * F + f] = s;"),
-    "adam_no_bias_correction": ("lr * (mom[i] / c1)", "lr * (mom[i])"),
+    "adam_no_bias_correction": ("double y = x[i] - lr * (mom[i] / c1)", "double y = x[i] - lr * (mom[i])"),
+    "gumbel_tie_to_one": ("xh[i] = s > 0.0f ? 1.0 : 0.0;", "xh[i] = s >= 0.0f ? 1.0 : 0.0;"),
+    "gumbel_single_logit_step": ("d[i] -= 2.0 * lr * g1;", "d[i] -= lr * g1;"),
+    "gumbel_no_temperature": ("const double g1 = G[i] * y1 * (1.0 - y1) / tau;",
+                              "const double g1 = G[i] * y1 * (1.0 - y1);"),
+    "gumbel_wrong_sigmoid": ("const double y1 = 1.0 / (1.0 + exp(-(d[i] + (double)l[i]) / tau));",
+                             "const double y1 = 1.0 / (1.0 + exp(-(d[i] - (double)l[i]) / tau));"),
     "sgd_no_upper_clamp": ("    if (y > 1.0) y = 1.0;\n    x[i] = y;\n  }\n}\n\n/* Adam",
                            "    x[i] = y;\n  }\n}\n\n/* Adam"),
     "def_mode_includes_self": ("if (i != j) others *= factor(c[i], xr);", "others *= factor(c[i], xr);"),
@@ -46,6 +53,9 @@ def _pins():
         lambda: P.test_unsat_count_with_ties_at_half(),
         lambda: P.test_best_is_first_minimum(),
         lambda: P.test_batch_equals_formulas_alone(),
+        lambda: Gp.test_step_matches_two_logit_autograd(True, 1.0),
+        lambda: Gp.test_step_matches_two_logit_autograd(False, 0.5),
+        lambda: Gp.test_tie_goes_to_state_zero(),
     ]
 
 
