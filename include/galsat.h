@@ -223,6 +223,40 @@ galsat_status galsat_gumbel_step(galsat_handle h, float* d, int32_t ldd, float* 
 galsat_status galsat_gumbel_noise(galsat_handle h, uint64_t seed, int32_t step, float* noise,
                                   int32_t ldn, void* stream);
 
+/* Hand-off to the CPU stage (Section 3.3).  Candidate pool, Eq. (8): for
+ * candidate k = 0 .. num-1 and every variable v of formula f, with
+ * r = best_restart[f] and l the noise difference of step k, restart 0 of
+ * the generator described at galsat_gumbel_step,
+ *   assign[k][v] = [d[v][r] + l > 0]            (FP32, tie -> 0)
+ *   conf[k][v]   = probability of that value under sigma((d + l) / tau).
+ *   d            device FP32 [n][ldd] (logit differences, or any score whose
+ *                sigmoid is the probability of the value 1)
+ *   best_restart device int32 [F]
+ *   assign       device uint8 [num][n];  conf  device FP32 [num][n] */
+galsat_status galsat_candidates(galsat_handle h, const float* d, int32_t ldd,
+                                const int32_t* best_restart, int32_t num, uint64_t seed, float tau,
+                                uint8_t* assign, float* conf, void* stream);
+
+/* Unperturbed confidence of the selected restart, for choosing branching
+ * variables (Section 3.3.2): conf[v] = max(p, 1 - p), p = sigma(d[v][r] / tau),
+ * r = best_restart[f(v)].  conf: device FP32 [n]. */
+galsat_status galsat_confidence(galsat_handle h, const float* d, int32_t ldd,
+                                const int32_t* best_restart, float tau, float* conf, void* stream);
+
+/* Per formula f and row k of conf ([num][n], device FP32), selects the
+ * S_f = min(n_f, max(min_count, ceil(frac * n_f))) most confident
+ * (highest = 1: the unit clauses of Eq. 9-10, frac 0.0005 in the appendix)
+ * or least confident (highest = 0, frac 0, min_count = d: the branching
+ * variables of Lemma 1, d = 7 in the appendix) variables, ties to the lower
+ * variable id, and writes their global ids in increasing order to
+ * out[k][offsets[f] .. offsets[f+1]).  offsets: HOST int32 [F+1], always
+ * filled (synchronously); out: device int32 [num][offsets[F]], or NULL to
+ * query the sizes only.  The call synchronises `stream` once (it uploads the
+ * offsets table). */
+galsat_status galsat_select_vars(galsat_handle h, const float* conf, int32_t num, int32_t highest,
+                                 float frac, int32_t min_count, int32_t* offsets, int32_t* out,
+                                 void* stream);
+
 /* Rounds x (x > 0.5 -> 1; an x that is already 0/1 is used as given),
  * counts unsatisfied clauses exactly per (formula, restart) with wavefront
  * ballot and popcount, and picks per formula the restart with the fewest
@@ -237,6 +271,21 @@ galsat_status galsat_round_check(galsat_handle h, const float* x, int32_t ldx, i
 /* Sets the Adam step counter (the next step uses t + 1); 0 restarts the bias
  * correction.  For checkpoint and resume. */
 galsat_status galsat_set_adam_step(galsat_handle h, int32_t t);
+
+/* Plan autotuner.  Derives candidate plans from the restart count (lanes
+ * per item and restarts per lane), the clause-length histogram (recompute
+ * threshold when clauses longer than 8 literals exist) and the formula
+ * count (chunks per formula of the XCD-aware order), creates a handle for
+ * each, times `steps` steps of galsat_step from a copy of x0 with HIP
+ * events on `stream`, and writes the fastest plan as a plan_override string
+ * to plan_out (host, plan_cap >= 64 bytes) and its time per step to
+ * *best_ms (may be NULL).  x0: device FP32 [n][ldx], not modified.  When the
+ * environment variable GALSAT_PLAN_CACHE names a file, the result is
+ * appended to it ("<shape key> | <plan>"), and galsat_create called without
+ * plan_override uses the plan recorded for the problem's shape. */
+galsat_status galsat_autotune(const galsat_problem* prob, const galsat_options* opt,
+                              const float* x0, int32_t ldx, int32_t steps, void* stream,
+                              char* plan_out, int32_t plan_cap, double* best_ms);
 
 /* Plan and size information (host values). */
 typedef struct {

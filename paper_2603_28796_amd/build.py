@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgalsat.so")
-SOURCES = ["galsat_kernels.hip", "galsat_host.hip", "galsat_tseitin.hip"]
+SOURCES = ["galsat_kernels.hip", "galsat_host.hip", "galsat_tseitin.hip", "galsat_tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -123,6 +123,7 @@ struct galsat_ctx {
   int schedule = GALSAT_SCHED_GENERAL;
   Tile tile;
   int tgroup = 1;    // restart tiles per launch of a gradient pass
+  int stream_items = 0;  // streaming variable pass
   int32_t ld = 0;    // internal state row stride (floats)
   int64_t ldD = 0;
   int adam_t = 0;
@@ -157,6 +158,7 @@ struct galsat_ctx {
   // workspace
   float *D = nullptr, *xa = nullptr, *xb = nullptr;
   float* nbuf = nullptr;  // noise of the straight-through Gumbel mode (allocated on first use)
+  int32_t* sel_off = nullptr;  // per-formula selection offsets of galsat_select_vars
   double* loss_part = nullptr;
   double* gseg = nullptr;
   int32_t* unsat_part = nullptr;
@@ -336,8 +338,10 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 }
 
 // Parses "key=value,key=value" plan overrides: lpi, rpl, krec, tg, xcdc
-// (chunks per formula of multi-formula launches; 0 turns the XCD order off).
-void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc) {
+// (chunks per formula of multi-formula launches; 0 turns the XCD order off),
+// stream (1: streaming variable pass).
+void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
+                    int* stream_items) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -354,6 +358,7 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "krec") *krec = v;
       else if (k == "tg") *tg = v;
       else if (k == "xcdc") *xcdc = v;
+      else if (k == "stream") *stream_items = v;
     }
     pos = comma + 1;
   }
@@ -401,6 +406,12 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   if (opt.partials < 0 || opt.partials > 2) return create_fail(GALSAT_EINVAL, "unknown partials mode");
   if (opt.schedule < 0 || opt.schedule > 3) return create_fail(GALSAT_EINVAL, "unknown schedule");
   if (!(opt.lr >= 0.0f) || !std::isfinite(opt.lr)) return create_fail(GALSAT_EINVAL, "lr must be finite and >= 0");
+
+  // a plan remembered by galsat_autotune for this problem's shape
+  std::string cached_plan;
+  if (!opt.plan_override && std::getenv("GALSAT_PLAN_CACHE") &&
+      plan_cache_lookup(plan_key(prob), &cached_plan))
+    opt.plan_override = cached_plan.c_str();
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   PhaseTimer ptimer;
@@ -526,8 +537,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   (void)hipGetDevice(&h->device);
 
   // ---- plan: which clauses recompute their partials in the variable pass
-  int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1;
-  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o);
+  int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1;
+  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o);
   const int64_t xcd_chunks = xcdc_o >= 0 ? xcdc_o : kXcdChunks;
   int32_t krec;
   if (opt.partials == GALSAT_PARTIALS_STORE) krec = -1;           // every clause stores
@@ -548,6 +559,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   }
   h->ld = (int32_t)round_up(R, 4);
   h->ldD = round_up(R, 4);
+  h->stream_items = stream_o >= 0 ? stream_o : 0;
   auto count_stored = [&](int32_t kr) {
     std::atomic<int64_t> c{0};
     parallel_for(m, [&](int64_t t0, int64_t t1) {
@@ -766,6 +778,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   }
   ptimer.mark("chunks");
   h->heavy_f_first = heavy_f_first;
+  h->opt.plan_override = nullptr;  // only read while planning
   h->n_heavy = (int32_t)heavy.size();
   h->n_seg = (int32_t)seg_var.size();
   // partial-sum rows of a step, contiguous per formula: its variable chunks,
@@ -948,6 +961,7 @@ VarPassArgs var_args(const galsat_ctx* h) {
   a.heavy_var = h->heavy_var;
   a.heavy_sbeg = h->heavy_sbeg;
   a.var_formula = h->var_formula;
+  a.stream_items = h->stream_items;
   a.D = h->D;
   a.ldD = h->ldD;
   a.loss_part = h->loss_part;
@@ -1294,6 +1308,72 @@ extern "C" galsat_status galsat_gumbel_step(galsat_handle h, float* d, int32_t l
                                    adam ? 1 : 0, s),
            "gumbel update");
   }
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_candidates(galsat_handle h, const float* d, int32_t ldd,
+                                           const int32_t* best_restart, int32_t num, uint64_t seed,
+                                           float tau, uint8_t* assign, float* conf, void* stream) {
+  GS_CHECK_HANDLE(h);
+  if (num < 0) return h->fail(GALSAT_EINVAL, "num must be >= 0");
+  if (num > 0 && h->n > 0 && (!d || !best_restart || !assign || !conf))
+    return h->fail(GALSAT_EINVAL, "d, best_restart, assign and conf are required");
+  if (ldd < h->R) return h->fail(GALSAT_EINVAL, "ldd < restarts");
+  if (!(tau > 0.0f) || !std::isfinite(tau)) return h->fail(GALSAT_EINVAL, "tau must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ProfScope _ps(h, GALSAT_K_SELECT, s);
+  GS_HIP(h, launch_candidates(d, ldd, h->var_formula, best_restart, h->n, num, seed, tau, assign, conf,
+                              s),
+         "candidates");
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_confidence(galsat_handle h, const float* d, int32_t ldd,
+                                           const int32_t* best_restart, float tau, float* conf,
+                                           void* stream) {
+  GS_CHECK_HANDLE(h);
+  if (h->n > 0 && (!d || !best_restart || !conf))
+    return h->fail(GALSAT_EINVAL, "d, best_restart and conf are required");
+  if (ldd < h->R) return h->fail(GALSAT_EINVAL, "ldd < restarts");
+  if (!(tau > 0.0f) || !std::isfinite(tau)) return h->fail(GALSAT_EINVAL, "tau must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ProfScope _ps(h, GALSAT_K_SELECT, s);
+  GS_HIP(h, launch_confidence(d, ldd, h->var_formula, best_restart, h->n, tau, conf, s), "confidence");
+  return GALSAT_OK;
+}
+
+extern "C" galsat_status galsat_select_vars(galsat_handle h, const float* conf, int32_t num,
+                                            int32_t highest, float frac, int32_t min_count,
+                                            int32_t* offsets, int32_t* out, void* stream) {
+  GS_CHECK_HANDLE(h);
+  if (!offsets) return h->fail(GALSAT_EINVAL, "offsets is NULL");
+  if (num < 0 || min_count < 0 || !(frac >= 0.0f && frac <= 1.0f))
+    return h->fail(GALSAT_EINVAL, "num, min_count >= 0 and frac in [0, 1] required");
+  std::vector<int32_t> off((size_t)h->F + 1, 0);
+  for (int32_t f = 0; f < h->F; ++f) {
+    const int32_t nf = h->h_fvb[f + 1] - h->h_fvb[f];
+    int64_t c = (int64_t)std::ceil((double)frac * (double)nf);
+    c = std::max<int64_t>(c, min_count);
+    c = std::min<int64_t>(c, nf);
+    off[f + 1] = off[f] + (int32_t)c;
+  }
+  std::memcpy(offsets, off.data(), off.size() * sizeof(int32_t));
+  if (!out) return GALSAT_OK;  // size query
+  if (!conf && num > 0) return h->fail(GALSAT_EINVAL, "conf is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!h->sel_off) {
+    hipError_t he = h->alloc(&h->sel_off, (size_t)h->F + 1);
+    if (he != hipSuccess) return h->dev_fail(he, "allocate selection offsets");
+  }
+  // the offsets table is tiny; upload it on the call's stream before the launch
+  GS_HIP(h, hipMemcpyAsync(h->sel_off, off.data(), off.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s),
+         "upload selection offsets");
+  GS_HIP(h, hipStreamSynchronize(s), "selection offsets");
+  ProfScope _ps(h, GALSAT_K_SELECT, s);
+  GS_HIP(h, launch_select(conf, h->n, h->F, h->f_vbeg, h->sel_off, off[h->F], num, highest != 0, out,
+                          s),
+         "select");
   return GALSAT_OK;
 }
 

@@ -44,6 +44,7 @@ struct VarPassArgs {
   int32_t chunk_base;           // first chunk of this launch
   int32_t tile_base;            // first restart tile of this launch
   int32_t tile_count;           // restart tiles of this launch (0: all from tile_base)
+  int32_t stream_items;         // 1: walk each slot's variables as one occurrence list
   const float* x;
   int32_t ldx;
   float* out;                   // next state (update modes) or gradient (grad mode)
@@ -98,6 +99,10 @@ struct FinalizeArgs {
 
 enum VarMode { kModeSGD = 0, kModeAdam = 1, kModeGrad = 2 };
 
+// Plan cache of the autotuner (galsat_tune.hip).
+std::string plan_key(const galsat_problem* prob);
+bool plan_cache_lookup(const std::string& key, std::string* plan);
+
 // Launchers (galsat_kernels.hip).  All return the launch's hipError_t.
 hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s);
 hipError_t launch_var_seg(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
@@ -129,6 +134,14 @@ hipError_t launch_gumbel_update(float* d, int32_t ldd, const float* nb, const fl
                                 float* mom, float* vel, int32_t ldm, int32_t n, int32_t R, float tau,
                                 float lr, float b1, float b2, float eps, double inv_c1,
                                 double inv_c2, int32_t adam, hipStream_t s);
+hipError_t launch_candidates(const float* d, int32_t ldd, const int32_t* var_formula,
+                             const int32_t* best, int32_t n, int32_t num, uint64_t seed, float tau,
+                             uint8_t* assign, float* conf, hipStream_t s);
+hipError_t launch_confidence(const float* d, int32_t ldd, const int32_t* var_formula,
+                             const int32_t* best, int32_t n, float tau, float* conf, hipStream_t s);
+hipError_t launch_select(const float* conf, int32_t n, int32_t F, const int32_t* f_vbeg,
+                         const int32_t* sel_off, int32_t stot, int32_t num, bool highest,
+                         int32_t* out, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s);
 
 }  // namespace galsat

@@ -412,6 +412,118 @@ __global__ __launch_bounds__(kBlock) void k_var_pass(VarPassArgs a) {
   block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], tile, a.R, a.loss_part, a.unsat_part);
 }
 
+// Streaming variant for small restart tiles: each item slot walks the
+// occurrences of a contiguous run of variables as one list, four records at
+// a time across variable boundaries, so a variable's last few occurrences
+// share a batch with the next variable's first ones instead of costing a
+// memory round trip each.  Sums and their order per variable are those of
+// k_var_pass.
+template <int RPL, int NO>
+__device__ __forceinline__ void inline4_products(const VarPassArgs& a, const int4 (&o)[4], int r0,
+                                                 float (&prod)[4][RPL], bool (&any_true)[4][RPL]) {
+  float y[4][NO][RPL];
+  int codes[4][NO];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int all[3] = {o[k].y, o[k].z, o[k].w};
+#pragma unroll
+    for (int c = 0; c < NO; ++c) {
+      codes[k][c] = all[c];
+      load_row<RPL>(a.x + (int64_t)(all[c] >> 1) * a.ldx + r0, y[k][c]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    combine<RPL, NO>(codes[k], y[k], rec_nother(o[k].x), rec_first(o[k].x), prod[k], any_true[k]);
+}
+
+template <int LPI, int RPL, int MODE>
+__global__ __launch_bounds__(kBlock) void k_var_stream(VarPassArgs a) {
+  constexpr int IPB = kBlock / LPI;
+  constexpr int RT = LPI * RPL;
+  const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
+  const int chunk =
+      a.chunk_order ? ldc(a.chunk_order, a.chunk_base + blockIdx.x) : a.chunk_base + blockIdx.x;
+  if (chunk < 0) return;  // padding of the XCD-aware order: the whole block leaves
+  const int tile = a.tile_base + blockIdx.y;
+  const int r0 = tile * RT + lane * RPL;
+  const bool active = r0 < a.R;
+  const int rc = active ? r0 : 0;
+  const int vb = ldc(a.chunk_vbeg, chunk), ve = ldc(a.chunk_vend, chunk);
+  // occurrence-balanced split of [vb, ve) into IPB contiguous runs
+  const int qB = ldc(a.var_ptr, vb), qE = ldc(a.var_ptr, ve);
+  auto split = [&](int s) -> int {  // first v in [vb, ve] with var_ptr[v] >= target
+    if (s <= 0) return vb;
+    if (s >= IPB) return ve;
+    const int target = qB + (int)((int64_t)(qE - qB) * s / IPB);
+    int lo = vb, hi = ve;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ldc(a.var_ptr, mid) < target) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  const int va = uniform<LPI>(split(slot)), vz = uniform<LPI>(split(slot + 1));
+  double lsum[RPL];
+  int usum[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) { lsum[j] = 0.0; usum[j] = 0; }
+
+  int v = va;
+  int cur_end = v < vz ? ldc(a.var_ptr, v + 1) : 0;
+  double g[RPL];
+  float xv[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) { g[j] = 0.0; xv[j] = 0.0f; }
+  if (v < vz) load_row<RPL>(a.x + (int64_t)v * a.ldx + rc, xv);
+  // finishes every variable whose occurrences end at or before position qpos
+  auto finish_before = [&](int qpos) {
+    while (v < vz && cur_end <= qpos) {
+      if (active) var_epilogue<RPL, MODE>(a, v, r0, xv, g);
+      ++v;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) g[j] = 0.0;
+      if (v < vz) {
+        cur_end = ldc(a.var_ptr, v + 1);
+        load_row<RPL>(a.x + (int64_t)v * a.ldx + rc, xv);
+      }
+    }
+  };
+  int q = va < vz ? ldc(a.var_ptr, va) : 0;
+  const int qz = va < vz ? ldc(a.var_ptr, vz) : 0;
+  finish_before(q);
+  while (q < qz) {
+    if (q + 4 <= qz) {
+      const int4 o[4] = {ldc4(a.occ, q), ldc4(a.occ, q + 1), ldc4(a.occ, q + 2),
+                         ldc4(a.occ, q + 3)};
+      const int kinds = rec_kind(o[0].x) | rec_kind(o[1].x) | rec_kind(o[2].x) | rec_kind(o[3].x);
+      const int most = max(max(rec_nother(o[0].x), rec_nother(o[1].x)),
+                           max(rec_nother(o[2].x), rec_nother(o[3].x)));
+      if (kinds == kRecInline && most <= 3) {
+        float prod[4][RPL];
+        bool any_true[4][RPL];
+        if (most <= 2)
+          inline4_products<RPL, 2>(a, o, rc, prod, any_true);
+        else
+          inline4_products<RPL, 3>(a, o, rc, prod, any_true);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          finish_before(q + k);
+          add_occurrence<RPL>(rec_neg(o[k].x), rec_first(o[k].x), prod[k], any_true[k], xv, g,
+                              lsum, usum);
+        }
+        q += 4;
+        continue;
+      }
+    }
+    finish_before(q);
+    one_occurrence<RPL>(a, ldc4(a.occ, q), q, rc, xv, g, lsum, usum);
+    ++q;
+  }
+  finish_before(qz);
+  block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], tile, a.R, a.loss_part, a.unsat_part);
+}
+
 // Segments of split variables (variables with more occurrences than one
 // item should serialise): each segment's partial gradient goes to
 // gseg[s][r] in FP64.
@@ -748,6 +860,121 @@ __global__ __launch_bounds__(256) void k_gumbel_update(float* d, int32_t ldd, co
   }
 }
 
+// ---------------------------------------------------------- hand-off
+//
+// Candidate pool of Section 3.3.1, Eq. (8): candidate k of formula f adds
+// the noise difference of "step" k, restart 0 to the logit difference of
+// f's selected restart and takes the argmax; its confidence is the
+// perturbed probability of the value taken.
+__global__ __launch_bounds__(256) void k_candidates(const float* d, int32_t ldd,
+                                                    const int32_t* var_formula, const int32_t* best,
+                                                    int32_t n, uint64_t seed, float tau,
+                                                    uint8_t* assign, float* conf) {
+  const int k = blockIdx.y;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int r = best[var_formula[v]];
+    const float dv = d[v * ldd + r];
+    const float l = gumbel_diff(seed, k, v, 0);
+    const bool one = dv + l > 0.0f;
+    const double y1 = 1.0 / (1.0 + exp(-((double)dv + (double)l) / (double)tau));
+    assign[(int64_t)k * n + v] = one ? 1 : 0;
+    conf[(int64_t)k * n + v] = (float)(one ? y1 : 1.0 - y1);
+  }
+}
+
+// Unperturbed confidence max(p, 1 - p), p = sigma(d / tau), of each
+// variable at its formula's selected restart (Section 3.3.2).
+__global__ __launch_bounds__(256) void k_confidence(const float* d, int32_t ldd,
+                                                    const int32_t* var_formula, const int32_t* best,
+                                                    int32_t n, float tau, float* conf) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const double p = 1.0 / (1.0 + exp(-(double)d[v * ldd + best[var_formula[v]]] / (double)tau));
+    conf[v] = (float)(p > 0.5 ? p : 1.0 - p);
+  }
+}
+
+// Selection of the S_f most (HIGH) or least confident variables of formula
+// f in candidate k, ties to the lower index, written in increasing index
+// order.  Keys are 64-bit: confidence bits (inverted for LOW) above the
+// inverted local index, so every key is distinct and larger = preferred.
+// An exact radix select (eight 8-bit digits, integer counts in LDS) finds
+// the S-th largest key; a block scan then compacts the selected indices.
+template <bool HIGH>
+__device__ __forceinline__ uint64_t sel_key(float c, int local) {
+  const uint32_t b = __float_as_uint(c);
+  const uint64_t hi = HIGH ? b : ~b;
+  return (hi << 32) | (uint64_t)(~(uint32_t)local);
+}
+
+template <bool HIGH>
+__global__ __launch_bounds__(1024) void k_select(const float* conf, int32_t n,
+                                                 const int32_t* f_vbeg, const int32_t* sel_off,
+                                                 int32_t stot, int32_t* out) {
+  const int f = blockIdx.x, k = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+  const int v0 = f_vbeg[f], nf = f_vbeg[f + 1] - v0;
+  const int S = sel_off[f + 1] - sel_off[f];
+  if (S <= 0) return;
+  const float* c = conf + (int64_t)k * n + v0;
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix, s_mask;
+  __shared__ int s_rank;
+  if (tid == 0) {
+    s_prefix = 0;
+    s_mask = 0;
+    s_rank = S;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    for (int b = tid; b < 256; b += nt) hist[b] = 0;
+    __syncthreads();
+    const uint64_t prefix = s_prefix, mask = s_mask;
+    for (int i = tid; i < nf; i += nt) {
+      const uint64_t key = sel_key<HIGH>(c[i], i);
+      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int rank = s_rank, acc = 0, chosen = 0;
+      for (int b = 255; b >= 0; --b) {
+        if (acc + (int)hist[b] >= rank) {
+          chosen = b;
+          rank -= acc;
+          break;
+        }
+        acc += (int)hist[b];
+      }
+      s_prefix = prefix | ((uint64_t)chosen << shift);
+      s_mask = mask | (0xFFULL << shift);
+      s_rank = rank;
+    }
+    __syncthreads();
+  }
+  const uint64_t thr = s_prefix;  // the S-th largest key: keys >= thr are the selection
+  __shared__ int cnt[1024];
+  const int per = (nf + nt - 1) / nt;
+  const int i0 = tid * per, i1 = min(nf, i0 + per);
+  int mine = 0;
+  for (int i = i0; i < i1; ++i) mine += sel_key<HIGH>(c[i], i) >= thr ? 1 : 0;
+  cnt[tid] = mine;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int t = 0; t < nt; ++t) {
+      const int x = cnt[t];
+      cnt[t] = acc;
+      acc += x;
+    }
+  }
+  __syncthreads();
+  int pos = cnt[tid];
+  int32_t* o = out + (int64_t)k * stot + sel_off[f];
+  for (int i = i0; i < i1; ++i)
+    if (sel_key<HIGH>(c[i], i) >= thr) o[pos++] = v0 + i;
+}
+
 // ------------------------------------------------------- round & count
 //
 // bits[w][v]: bit l = [x[v][64w + l] > 0.5] packed by one wavefront ballot.
@@ -841,6 +1068,14 @@ namespace {
 template <int LPI, int RPL>
 hipError_t var_pass_rpl(const VarPassArgs& a, int mode, int chunks, int tiles, hipStream_t s) {
   dim3 grid(chunks, tiles), block(kBlock);
+  if (a.stream_items) {
+    switch (mode) {
+      case kModeSGD: hipLaunchKernelGGL((k_var_stream<LPI, RPL, kModeSGD>), grid, block, 0, s, a); break;
+      case kModeAdam: hipLaunchKernelGGL((k_var_stream<LPI, RPL, kModeAdam>), grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_var_stream<LPI, RPL, kModeGrad>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+  }
   switch (mode) {
     case kModeSGD: hipLaunchKernelGGL((k_var_pass<LPI, RPL, kModeSGD>), grid, block, 0, s, a); break;
     case kModeAdam: hipLaunchKernelGGL((k_var_pass<LPI, RPL, kModeAdam>), grid, block, 0, s, a); break;
@@ -1056,6 +1291,36 @@ hipError_t launch_gumbel_update(float* d, int32_t ldd, const float* nb, const fl
   dim3 grid(grid_x_for(((int64_t)n + 3) / 4), (R + 63) / 64), block(256);
   hipLaunchKernelGGL(k_gumbel_update, grid, block, 0, s, d, ldd, nb, G, ld, mom, vel, ldm, n, R, tau,
                      lr, b1, b2, eps, inv_c1, inv_c2, adam);
+  return hipGetLastError();
+}
+
+hipError_t launch_candidates(const float* d, int32_t ldd, const int32_t* var_formula,
+                             const int32_t* best, int32_t n, int32_t num, uint64_t seed, float tau,
+                             uint8_t* assign, float* conf, hipStream_t s) {
+  if (n <= 0 || num <= 0) return hipSuccess;
+  dim3 grid(grid_x_for(((int64_t)n + 255) / 256), num), block(256);
+  hipLaunchKernelGGL(k_candidates, grid, block, 0, s, d, ldd, var_formula, best, n, seed, tau, assign,
+                     conf);
+  return hipGetLastError();
+}
+
+hipError_t launch_confidence(const float* d, int32_t ldd, const int32_t* var_formula,
+                             const int32_t* best, int32_t n, float tau, float* conf, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_confidence, dim3(grid_x_for(((int64_t)n + 255) / 256)), dim3(256), 0, s, d,
+                     ldd, var_formula, best, n, tau, conf);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const float* conf, int32_t n, int32_t F, const int32_t* f_vbeg,
+                         const int32_t* sel_off, int32_t stot, int32_t num, bool highest,
+                         int32_t* out, hipStream_t s) {
+  if (F <= 0 || num <= 0 || stot <= 0) return hipSuccess;
+  dim3 grid(F, num), block(1024);
+  if (highest)
+    hipLaunchKernelGGL((k_select<true>), grid, block, 0, s, conf, n, f_vbeg, sel_off, stot, out);
+  else
+    hipLaunchKernelGGL((k_select<false>), grid, block, 0, s, conf, n, f_vbeg, sel_off, stot, out);
   return hipGetLastError();
 }
 

@@ -77,9 +77,11 @@ class _Info(ctypes.Structure):
 # every symbol include/galsat.h declares
 EXPORTS = ("galsat_default_options", "galsat_create", "galsat_destroy", "galsat_init_state",
            "galsat_loss_grad", "galsat_step", "galsat_step_prepare", "galsat_gumbel_step",
-           "galsat_gumbel_noise", "galsat_round_check",
+           "galsat_gumbel_noise", "galsat_candidates", "galsat_confidence",
+           "galsat_select_vars", "galsat_round_check",
            "galsat_set_adam_step",
-           "galsat_get_info", "galsat_profile", "galsat_kernel_times", "galsat_tseitin",
+           "galsat_autotune", "galsat_get_info", "galsat_profile", "galsat_kernel_times",
+           "galsat_tseitin",
            "galsat_status_string", "galsat_last_error")
 
 KERNEL_KINDS = ("var_pass", "clause_pass", "finalize", "copy", "pack", "count", "select",
@@ -120,12 +122,19 @@ def load_library(path: Optional[str] = None):
     lib.galsat_gumbel_step.argtypes = [_P, _P, _I32, _P, ctypes.c_uint64, _I32, _I32,
                                        ctypes.c_float, _P, _P, _P, _P]
     lib.galsat_gumbel_noise.argtypes = [_P, ctypes.c_uint64, _I32, _P, _I32, _P]
+    lib.galsat_candidates.argtypes = [_P, _P, _I32, _P, _I32, ctypes.c_uint64, ctypes.c_float, _P,
+                                      _P, _P]
+    lib.galsat_confidence.argtypes = [_P, _P, _I32, _P, ctypes.c_float, _P, _P]
+    lib.galsat_select_vars.argtypes = [_P, _P, _I32, _I32, ctypes.c_float, _I32, _P, _P, _P]
     lib.galsat_round_check.argtypes = [_P, _P, _I32, _P, _P, _P, _P]
     lib.galsat_set_adam_step.argtypes = [_P, _I32]
     lib.galsat_get_info.argtypes = [_P, ctypes.POINTER(_Info)]
     lib.galsat_profile.argtypes = [_P, _I32]
     lib.galsat_kernel_times.argtypes = [_P, ctypes.POINTER(_KernelTimes)]
     lib.galsat_tseitin.argtypes = [_I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]
+    lib.galsat_autotune.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), _P, _I32,
+                                    _I32, _P, ctypes.c_char_p, _I32, ctypes.POINTER(ctypes.c_double)]
+    lib.galsat_autotune.restype = ctypes.c_int
     lib.galsat_tseitin.restype = ctypes.c_int
     lib.galsat_status_string.argtypes = [ctypes.c_int]
     lib.galsat_status_string.restype = ctypes.c_char_p
@@ -133,6 +142,7 @@ def load_library(path: Optional[str] = None):
     lib.galsat_last_error.restype = ctypes.c_char_p
     for fn in ("galsat_create", "galsat_destroy", "galsat_init_state", "galsat_loss_grad",
                "galsat_step", "galsat_step_prepare", "galsat_gumbel_step", "galsat_gumbel_noise",
+               "galsat_candidates", "galsat_confidence", "galsat_select_vars",
                "galsat_round_check", "galsat_set_adam_step",
                "galsat_get_info",
                "galsat_profile", "galsat_kernel_times"):
@@ -156,6 +166,48 @@ def _state_ld(x: torch.Tensor, n: int, R: int, name: str = "x") -> int:
     if x.shape[0] != n or x.shape[1] < R or x.stride(1) != 1 or (n > 1 and x.stride(0) < R):
         raise ValueError(f"{name} must be [n={n}, ld>={R}] with unit column stride")
     return int(x.stride(0)) if n > 1 else int(max(x.shape[1], R))
+
+
+def _structs(cnf, restarts, optimizer="sgd", lr=0.1, beta1=0.9, beta2=0.999, eps=1e-8,
+             partials="auto", recompute_max_len=0, workspace_budget_bytes=0, validate=True,
+             schedule="auto", use_graph=False, plan_override=None):
+    """(problem struct, options struct, arrays kept alive)."""
+    lib = load_library()
+    keep = [np.ascontiguousarray(a, dtype=np.int32) for a in
+            (cnf.formula_var_begin, cnf.formula_clause_begin, cnf.clause_ptr, cnf.clause_lits,
+             cnf.var_ptr, cnf.var_occ)]
+    fvb, fcb, cp, cl, vp, vo = keep
+    prob = _Problem(cnf.F, fvb.ctypes.data, fcb.ctypes.data, cnf.n, cnf.m, cnf.L,
+                    cp.ctypes.data, cl.ctypes.data, vp.ctypes.data, vo.ctypes.data, int(restarts), 0)
+    opt = _Options()
+    lib.galsat_default_options(ctypes.byref(opt))
+    opt.optimizer = OPT[optimizer]
+    opt.lr, opt.beta1, opt.beta2, opt.eps = lr, beta1, beta2, eps
+    opt.partials = PARTIALS[partials]
+    opt.recompute_max_len = recompute_max_len
+    opt.workspace_budget_bytes = workspace_budget_bytes
+    opt.validate = 1 if validate else 0
+    opt.schedule = SCHEDULE[schedule]
+    opt.use_graph = 1 if use_graph else 0
+    ov = plan_override.encode() if plan_override else None
+    keep.append(ov)
+    opt.plan_override = ov
+    return prob, opt, keep
+
+
+def autotune(cnf, restarts: int, x0: torch.Tensor, steps: int = 5, **options):
+    """Time the candidate plans on `steps` real steps from x0; returns
+    (plan string, ms per step)."""
+    lib = load_library()
+    prob, opt, keep = _structs(cnf, restarts, **options)
+    ld = _state_ld(x0, cnf.n, int(restarts), "x0")
+    buf = ctypes.create_string_buffer(256)
+    best = ctypes.c_double()
+    st = lib.galsat_autotune(ctypes.byref(prob), ctypes.byref(opt), _ptr(x0), ld, int(steps),
+                             _stream(), buf, 256, ctypes.byref(best))
+    if st != 0:
+        raise GalsatError(st, "galsat_autotune", lib.galsat_last_error(None).decode())
+    return buf.value.decode(), best.value
 
 
 class Problem:
@@ -306,6 +358,41 @@ class Problem:
                                                   _ptr(out), out.shape[1], _stream()),
                     "galsat_gumbel_noise")
         return out
+
+    def candidates(self, d: torch.Tensor, best: torch.Tensor, num: int = 100, seed: int = 0,
+                   tau: float = 1.0):
+        """Candidate pool (Eq. 8): (assign [num, n] uint8, conf [num, n])."""
+        ld = _state_ld(d, self.n, self.R, "d")
+        best = best.to(device=d.device, dtype=torch.int32).contiguous()
+        assign = torch.empty((num, self.n), dtype=torch.uint8, device=d.device)
+        conf = torch.empty((num, self.n), dtype=torch.float32, device=d.device)
+        self._check(self._lib.galsat_candidates(self._h, _ptr(d), ld, _ptr(best), int(num),
+                                                ctypes.c_uint64(seed), float(tau), _ptr(assign),
+                                                _ptr(conf), _stream()), "galsat_candidates")
+        return assign, conf
+
+    def confidence(self, d: torch.Tensor, best: torch.Tensor, tau: float = 1.0) -> torch.Tensor:
+        ld = _state_ld(d, self.n, self.R, "d")
+        best = best.to(device=d.device, dtype=torch.int32).contiguous()
+        conf = torch.empty((1, self.n), dtype=torch.float32, device=d.device)
+        self._check(self._lib.galsat_confidence(self._h, _ptr(d), ld, _ptr(best), float(tau),
+                                                _ptr(conf), _stream()), "galsat_confidence")
+        return conf
+
+    def select_vars(self, conf: torch.Tensor, highest: bool = True, frac: float = 0.0005,
+                    min_count: int = 1):
+        """Returns (offsets [F+1] numpy, ids [num, offsets[-1]] int32 tensor)."""
+        conf = conf.to(dtype=torch.float32).contiguous()
+        num = conf.shape[0]
+        off = np.zeros(self.F + 1, dtype=np.int32)
+        self._check(self._lib.galsat_select_vars(self._h, None, num, 1 if highest else 0,
+                                                 float(frac), int(min_count), off.ctypes.data, None,
+                                                 _stream()), "galsat_select_vars")
+        out = torch.empty((num, max(int(off[-1]), 1)), dtype=torch.int32, device=conf.device)
+        self._check(self._lib.galsat_select_vars(self._h, _ptr(conf), num, 1 if highest else 0,
+                                                 float(frac), int(min_count), off.ctypes.data,
+                                                 _ptr(out), _stream()), "galsat_select_vars")
+        return off, out[:, :int(off[-1])]
 
     def prepare(self, x: torch.Tensor, steps: int, loss_trace: Optional[torch.Tensor] = None,
                 unsat_trace: Optional[torch.Tensor] = None):

@@ -81,12 +81,22 @@ def test_parity_cases(case, R, partials):
 
 @pytest.mark.parametrize("lpi", [4, 8, 16, 32, 64])
 @pytest.mark.parametrize("rpl", [1, 2, 4])
-def test_tile_overrides(lpi, rpl):
-    say(f"[tiles] lpi={lpi} rpl={rpl}")
-    cnf = CASES["edge"]()
+@pytest.mark.parametrize("stream", [0, 1])
+def test_tile_overrides(lpi, rpl, stream):
+    say(f"[tiles] lpi={lpi} rpl={rpl} stream={stream}")
+    cnf = CASES["edge"]() if lpi % 8 else CASES["batch"]()
     R = 40
-    prob = Problem(cnf, R, partials="auto", recompute_max_len=4, plan_override=f"lpi={lpi},rpl={rpl}")
-    parity_at(prob, cnf, _x0(cnf.n, R, 5), f"lpi={lpi} rpl={rpl}")
+    plan = f"lpi={lpi},rpl={rpl},stream={stream}"
+    prob = Problem(cnf, R, partials="auto", recompute_max_len=4, plan_override=plan)
+    parity_at(prob, cnf, _x0(cnf.n, R, 5), plan)
+    # the streaming walk sums every gradient in the same order as the default
+    ref = Problem(cnf, R, partials="auto", recompute_max_len=4,
+                  plan_override=f"lpi={lpi},rpl={rpl},stream=0")
+    x = _x0(cnf.n, R, 6)
+    _, g1 = prob.loss_grad(x)
+    _, g0 = ref.loss_grad(x)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g0)
 
 
 def test_unaligned_and_padded_state():
@@ -290,3 +300,24 @@ def test_graph_replay_matches_eager():
         assert torch.equal(xe, xg), f"replay {rep}: state differs"
         assert torch.equal(lt_e, lt_g) and torch.equal(ut_e, ut_g), f"replay {rep}: traces differ"
         del junk
+
+
+def test_autotune_and_plan_cache(tmp_path, monkeypatch):
+    """The autotuner returns one of its candidate plans; with a plan cache a
+    later galsat_create without a plan override uses the recorded plan."""
+    say("[autotune]")
+    from paper_2603_28796_amd.galsat import autotune
+    cnf = CASES["long_mix"]()
+    R = 16
+    cache = tmp_path / "plans.txt"
+    monkeypatch.setenv("GALSAT_PLAN_CACHE", str(cache))
+    x0 = _x0(cnf.n, R, 99)
+    plan, ms = autotune(cnf, R, x0, steps=2)
+    assert ms > 0 and "lpi=" in plan and "krec=" in plan
+    assert plan in cache.read_text()
+    prob = Problem(cnf, R)
+    info = prob.info()
+    want = dict(kv.split("=") for kv in plan.split(","))
+    assert info["lanes_per_item"] == int(want["lpi"])
+    assert info["restarts_per_lane"] == int(want["rpl"])
+    parity_at(prob, cnf, x0, f"autotuned {plan}")
