@@ -114,15 +114,13 @@ enum { GALSAT_OPT_SGD_CLAMP = 0, GALSAT_OPT_ADAM = 1 };
 enum { GALSAT_PARTIALS_AUTO = 0, GALSAT_PARTIALS_STORE = 1, GALSAT_PARTIALS_RECOMPUTE = 2 };
 
 /* Execution schedule of galsat_step:
- *   GENERAL  multi-kernel passes per step over all formulas at once;
- *   BATCHED  one persistent launch runs every step for every
- *            (formula, restart group) work item with that item's state in
- *            LDS (formulas too large for LDS fall back to GENERAL);
+ *   GENERAL  multi-kernel passes per step over all formulas at once (the
+ *            formulas' work items share every launch);
  *   PLAIN    one formula at a time, kernels launched per pass per step
  *            (the reference point for batching, not a fast path);
- *   AUTO     BATCHED when every formula fits LDS, else GENERAL. */
-enum { GALSAT_SCHED_AUTO = 0, GALSAT_SCHED_GENERAL = 1, GALSAT_SCHED_BATCHED = 2,
-       GALSAT_SCHED_PLAIN = 3 };
+ *   AUTO     GENERAL.
+ * The value 2 is not used; galsat_create rejects it. */
+enum { GALSAT_SCHED_AUTO = 0, GALSAT_SCHED_GENERAL = 1, GALSAT_SCHED_PLAIN = 3 };
 
 typedef struct {
   int32_t optimizer;         /* GALSAT_OPT_*; default SGD_CLAMP */
@@ -134,8 +132,12 @@ typedef struct {
   int32_t validate;          /* 1 (default): also check that var_occ is a permutation */
   int32_t schedule;          /* GALSAT_SCHED_*; default AUTO */
   int32_t use_graph;         /* 1: galsat_step replays a captured hipGraph (GENERAL) */
-  const char* plan_override; /* NULL, or "lpi=L,rpl=P,krec=K": lanes per item
-                              (4..64), restarts per lane (1, 2, 4), recompute threshold */
+  const char* plan_override; /* NULL, or comma-separated key=value pairs:
+                              lpi lanes per item (4..64), rpl restarts per lane (1, 2,
+                              4), krec recompute threshold, tg restart tiles per launch,
+                              xcdc chunks per formula of the XCD-aware order (0: off),
+                              stream (1: streaming variable pass), two (1: two-phase
+                              gradient, 0: single pass; default: the plan's choice) */
 } galsat_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -274,8 +276,9 @@ galsat_status galsat_set_adam_step(galsat_handle h, int32_t t);
 
 /* Plan autotuner.  Derives candidate plans from the restart count (lanes
  * per item and restarts per lane), the clause-length histogram (recompute
- * threshold when clauses longer than 8 literals exist) and the formula
- * count (chunks per formula of the XCD-aware order), creates a handle for
+ * threshold when clauses longer than 8 literals exist), the formula
+ * count (chunks per formula of the XCD-aware order) and, for at most 64
+ * restarts, single pass against two-phase gradient; creates a handle for
  * each, times `steps` steps of galsat_step from a copy of x0 with HIP
  * events on `stream`, and writes the fastest plan as a plan_override string
  * to plan_out (host, plan_cap >= 64 bytes) and its time per step to
@@ -297,7 +300,7 @@ typedef struct {
   int32_t lanes_per_item;       /* restarts lanes of one variable or clause */
   int32_t restarts_per_lane;
   int32_t var_chunks, clause_chunks;
-  int32_t batched_items;        /* work items of the BATCHED schedule */
+  int32_t two_phase;            /* 1: the gradient runs as occurrence pass + variable sum */
   size_t device_bytes;          /* device memory held by the handle */
   int32_t adam_step;
 } galsat_info;
@@ -319,8 +322,9 @@ enum {
   GALSAT_K_PACK = 4,         /* rounding bit-pack (ballot) */
   GALSAT_K_COUNT = 5,        /* unsat count (ballot + popcount) */
   GALSAT_K_SELECT = 6,       /* best restart and its assignment */
-  GALSAT_K_BATCHED = 7,      /* persistent batched step loop */
-  GALSAT_K_KINDS = 8
+  GALSAT_K_OCC_PASS = 7,     /* two-phase plan: occurrence-parallel contributions */
+  GALSAT_K_VAR_SUM = 8,      /* two-phase plan: per-variable sums + fused update */
+  GALSAT_K_KINDS = 9
 };
 
 typedef struct {

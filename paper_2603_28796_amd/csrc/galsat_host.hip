@@ -29,6 +29,7 @@ thread_local std::string g_create_error;
 
 constexpr int kDefaultRecomputeMaxLen = 8;
 constexpr int kTargetBlocks = 2048;  // blocks per general-pass launch (256 CUs x 8)
+constexpr double kTwoPhaseSkew = 2.0;  // degree skew above which narrow batches go two-phase
 constexpr int64_t kCacheBudgetBytes = 256ll << 20;  // state rows one launch may gather from
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 constexpr int64_t kXcdChunks = 160;                 // workgroups resident on one XCD (about)
@@ -124,6 +125,7 @@ struct galsat_ctx {
   Tile tile;
   int tgroup = 1;    // restart tiles per launch of a gradient pass
   int stream_items = 0;  // streaming variable pass
+  int two_phase = 0;     // occurrence pass + variable sum instead of the single pass
   int32_t ld = 0;    // internal state row stride (floats)
   int64_t ldD = 0;
   int adam_t = 0;
@@ -133,6 +135,7 @@ struct galsat_ctx {
   std::vector<int32_t> h_fvb, h_fcb;
   Chunks vch, sch, ach;  // var chunks, stored-clause chunks, all-clause chunks
   Chunks segch;          // chunks of segments of split variables
+  Chunks och;            // occurrence-range chunks of the two-phase plan
   std::vector<int32_t> heavy_f_first;  // [F+1] split variables of each formula
   int32_t n_heavy = 0, n_seg = 0, step_rows = 0;
 
@@ -143,6 +146,10 @@ struct galsat_ctx {
   int32_t *lit_dslot = nullptr, *var_formula = nullptr, *stored_ids = nullptr;
   int32_t *vch_beg = nullptr, *vch_end = nullptr, *vch_row = nullptr, *vch_order = nullptr;
   int32_t n_vorder = 0;  // entries of vch_order (0: launch chunks in index order)
+  int32_t *och_beg = nullptr, *och_end = nullptr, *och_row = nullptr, *och_order = nullptr;
+  int32_t n_oorder = 0;
+  int32_t* occ_own = nullptr;  // [L] variable of each variable-major slot (two-phase)
+  int32_t* var_perm = nullptr;  // cost-sorted item order of the variable chunks, or null
   int32_t *sch_beg = nullptr, *sch_end = nullptr, *sch_row = nullptr;
   int32_t *segch_beg = nullptr, *segch_end = nullptr, *segch_row = nullptr;
   int32_t *ach_beg = nullptr, *ach_end = nullptr;
@@ -339,9 +346,10 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 
 // Parses "key=value,key=value" plan overrides: lpi, rpl, krec, tg, xcdc
 // (chunks per formula of multi-formula launches; 0 turns the XCD order off),
-// stream (1: streaming variable pass).
+// stream (1: streaming variable pass), two (1: two-phase gradient), dsort
+// (1: cost-sorted variable items), csort (1: length-sorted stored clauses).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
-                    int* stream_items) {
+                    int* stream_items, int* two_phase, int* dsort, int* csort) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -359,6 +367,9 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "tg") *tg = v;
       else if (k == "xcdc") *xcdc = v;
       else if (k == "stream") *stream_items = v;
+      else if (k == "two") *two_phase = v;
+      else if (k == "dsort") *dsort = v;
+      else if (k == "csort") *csort = v;
     }
     pos = comma + 1;
   }
@@ -404,7 +415,9 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   if (opt.optimizer != GALSAT_OPT_SGD_CLAMP && opt.optimizer != GALSAT_OPT_ADAM)
     return create_fail(GALSAT_EINVAL, "unknown optimizer");
   if (opt.partials < 0 || opt.partials > 2) return create_fail(GALSAT_EINVAL, "unknown partials mode");
-  if (opt.schedule < 0 || opt.schedule > 3) return create_fail(GALSAT_EINVAL, "unknown schedule");
+  if (opt.schedule != GALSAT_SCHED_AUTO && opt.schedule != GALSAT_SCHED_GENERAL &&
+      opt.schedule != GALSAT_SCHED_PLAIN)
+    return create_fail(GALSAT_EINVAL, "unknown schedule");
   if (!(opt.lr >= 0.0f) || !std::isfinite(opt.lr)) return create_fail(GALSAT_EINVAL, "lr must be finite and >= 0");
 
   // a plan remembered by galsat_autotune for this problem's shape
@@ -537,17 +550,52 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   (void)hipGetDevice(&h->device);
 
   // ---- plan: which clauses recompute their partials in the variable pass
-  int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1;
-  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o);
+  int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
+  int dsort_o = -1, csort_o = -1;
+  apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
+                 &dsort_o, &csort_o);
+  const bool csort = csort_o != 0;
   const int64_t xcd_chunks = xcdc_o >= 0 ? xcdc_o : kXcdChunks;
   int32_t krec;
   if (opt.partials == GALSAT_PARTIALS_STORE) krec = -1;           // every clause stores
   else if (opt.partials == GALSAT_PARTIALS_RECOMPUTE) krec = kmax;
   else krec = opt.recompute_max_len > 0 ? opt.recompute_max_len : kDefaultRecomputeMaxLen;
   if (krec_o >= -1 && opt.plan_override && std::strstr(opt.plan_override, "krec=")) krec = krec_o;
+  h->ld = (int32_t)round_up(R, 4);
+  h->ldD = round_up(R, 4);
+  h->stream_items = stream_o >= 0 ? stream_o : 0;
+  // Two-phase gradient (occurrence pass + variable sums): by default for
+  // narrow restart batches (at most 32) on instances whose occurrence counts
+  // are skewed, where the single pass's waves wait on their costliest
+  // variable.  Skew = mean degree seen by an occurrence / mean degree per
+  // variable (about 1 + 1/mean for Poisson degrees).  It needs one
+  // contribution row per occurrence.
+  {
+    double s1 = 0.0, s2 = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+      const double d = (double)(vp[v + 1] - vp[v]);
+      s1 += d;
+      s2 += d * d;
+    }
+    const double skew = (s1 > 0.0 && n > 0) ? (s2 / s1) / (s1 / n) : 1.0;
+    h->two_phase = two_o >= 0 ? (two_o ? 1 : 0) : ((R <= 32 && skew > kTwoPhaseSkew) ? 1 : 0);
+  }
+  if (h->two_phase && opt.workspace_budget_bytes > 0 &&
+      (size_t)L * (size_t)h->ldD * sizeof(float) > opt.workspace_budget_bytes)
+    h->two_phase = 0;
+  if (h->stream_items) h->two_phase = 0;
   h->tile = choose_tile(R, 4);
+  if (h->two_phase && R % 4 == 0 && R >= 16) {
+    // four restarts per lane measured faster for the two-phase passes
+    h->tile.rpl = 4;
+    h->tile.lpi = std::max(4, std::min(64, pow2_ceil(R / 4)));
+  }
   if (lpi_o == 4 || lpi_o == 8 || lpi_o == 16 || lpi_o == 32 || lpi_o == 64) h->tile.lpi = lpi_o;
   if ((rpl_o == 1 || rpl_o == 2 || rpl_o == 4) && R % rpl_o == 0) h->tile.rpl = rpl_o;
+  // Cost-sorted variable items when a wave holds several items (with a
+  // whole wave per item the index order keeps neighbouring variables, and
+  // their shared clauses, together).
+  const bool dsort = dsort_o >= 0 ? dsort_o > 0 : h->tile.lpi < 64;
   // Restart tiles per launch: keep the state rows a launch gathers from
   // (n x tiles x tile x 4 B) within a share of the 256 MB last-level cache.
   {
@@ -557,9 +605,6 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     if (tg_o > 0) tg = tg_o;
     h->tgroup = std::min(tg, tiles_all);
   }
-  h->ld = (int32_t)round_up(R, 4);
-  h->ldD = round_up(R, 4);
-  h->stream_items = stream_o >= 0 ? stream_o : 0;
   auto count_stored = [&](int32_t kr) {
     std::atomic<int64_t> c{0};
     parallel_for(m, [&](int64_t t0, int64_t t1) {
@@ -592,6 +637,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   std::unique_ptr<int4[]> occx(new int4[need_x ? (size_t)L + 1 : 1]);
   std::unique_ptr<int32_t[]> occ_cost(new int32_t[(size_t)L + 1]);
   std::unique_ptr<int32_t[]> lit_dslot(new int32_t[stored > 0 ? (size_t)L + 1 : 1]);
+  const bool two = h->two_phase != 0;
   {
     std::vector<int64_t> sbase((size_t)n + 1, 0);
     parallel_for(n, [&](int64_t v0, int64_t v1) {
@@ -613,9 +659,12 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
         const int32_t p = vo[q], t = clause_of[p], k = cp[t + 1] - cp[t];
         const int32_t sign_first = ((cl[p] & 1) << 3) | ((p == cp[t]) ? 16 : 0);
         if (k > krec) {
-          occ4[q] = make_int4(2 << 5, (int32_t)d, 0, 0);
+          // two-phase: the clause pass writes the contribution straight into
+          // the slot's row of the contribution buffer
+          const int32_t row = two ? q : (int32_t)d;
+          occ4[q] = make_int4(2 << 5, row, 0, 0);
           occ_cost[q] = 1;
-          lit_dslot[p] = (int32_t)d;
+          lit_dslot[p] = row;
           ++d;
         } else if (k <= 8) {
           int32_t codes[7] = {2 * v, 2 * v, 2 * v, 2 * v, 2 * v, 2 * v, 2 * v};
@@ -641,6 +690,11 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     f_sbeg[f] = (int64_t)stored_ids.size();
     for (int32_t t = fcb[f]; t < fcb[f + 1]; ++t)
       if (cp[t + 1] - cp[t] > krec && cp[t + 1] > cp[t]) stored_ids.push_back(t);
+    // longest first, so the clauses sharing a wave have similar lengths
+    if (csort)
+      std::stable_sort(stored_ids.begin() + f_sbeg[f], stored_ids.end(), [&](int32_t a2, int32_t b2) {
+        return cp[a2 + 1] - cp[a2] > cp[b2 + 1] - cp[b2];
+      });
   }
   f_sbeg[F] = (int64_t)stored_ids.size();
 
@@ -652,7 +706,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   const int tiles = (R + h->tile.tile() - 1) / h->tile.tile();
   const int64_t chunks_target = std::max<int64_t>(1, kTargetBlocks / std::max(1, tiles));
   const int ipb = kBlock / h->tile.lpi;
-  std::vector<int32_t> heavy, heavy_sbeg{0}, seg_var, seg_q0, seg_q1, vorder;
+  std::vector<int32_t> heavy, heavy_sbeg{0}, seg_var, seg_q0, seg_q1, vorder, oorder, vperm;
   std::vector<int32_t> heavy_f_first((size_t)F + 1, 0);
   {
     std::vector<int64_t> vcost((size_t)n, 1);
@@ -743,7 +797,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     // formulas are split into 8 groups of balanced cost (longest first) and
     // group x's chunks are placed at indices x, x + 8, x + 16, ...; padding
     // indices (-1) do nothing.
-    if (F > 1 && !per_formula && xcd_chunks > 0) {
+    auto xcd_order = [&](const Chunks& ch, std::vector<int32_t>* order) {
       std::vector<int32_t> ford(F);
       for (int32_t f = 0; f < F; ++f) ford[f] = f;
       std::stable_sort(ford.begin(), ford.end(),
@@ -753,17 +807,66 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       for (int32_t f : ford) {
         const int gsel = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[gsel] += fcost[f];
-        for (int32_t cid = vc.f_first[f]; cid < vc.f_first[f + 1]; ++cid) lists[gsel].push_back(cid);
+        for (int32_t cid = ch.f_first[f]; cid < ch.f_first[f + 1]; ++cid) lists[gsel].push_back(cid);
       }
       size_t longest = 0;
       for (auto& l : lists) longest = std::max(longest, l.size());
-      vorder.assign(longest * kXcds, -1);
+      order->assign(longest * kXcds, -1);
       for (int gsel = 0; gsel < kXcds; ++gsel)
-        for (size_t i = 0; i < lists[gsel].size(); ++i) vorder[i * kXcds + gsel] = lists[gsel][i];
+        for (size_t i = 0; i < lists[gsel].size(); ++i) (*order)[i * kXcds + gsel] = lists[gsel][i];
+    };
+    const bool xcd = F > 1 && !per_formula && xcd_chunks > 0;
+    if (xcd) xcd_order(vc, &vorder);
+    if (dsort) {
+      // item order within each variable chunk: costliest first, so the
+      // variables sharing a wave have similar occurrence counts
+      vperm.resize((size_t)n);
+      for (int32_t v = 0; v < n; ++v) vperm[v] = v;
+      parallel_for(vc.count(), [&](int64_t c0, int64_t c1) {
+        for (int64_t cc = c0; cc < c1; ++cc)
+          std::stable_sort(vperm.begin() + vc.beg[cc], vperm.begin() + vc.end[cc],
+                           [&](int32_t a2, int32_t b2) { return vcost[a2] > vcost[b2]; });
+      });
     }
     heavy_f_first[F] = (int32_t)heavy.size();
     h->vch = vc;
     h->segch = sc;
+    if (two) {
+      // occurrence chunks of the two-phase plan: ranges of variable-major
+      // slots of about equal gather cost (+1 per slot for its row store)
+      Chunks oc;
+      oc.f_first.assign((size_t)F + 1, 0);
+      int64_t ototal = 0;
+      std::vector<int64_t> focost((size_t)F, 0);
+      for (int32_t f = 0; f < F; ++f) {
+        int64_t cf = 0;
+        for (int32_t q = vp[fvb[f]]; q < vp[fvb[f + 1]]; ++q) cf += occ_cost[q] + 1;
+        focost[f] = cf;
+        ototal += cf;
+      }
+      const int64_t otarget = std::max<int64_t>(64, ototal / chunks_target);
+      for (int32_t f = 0; f < F; ++f) {
+        oc.f_first[f] = oc.count();
+        int64_t tf = otarget;
+        if (per_formula) tf = std::max<int64_t>(64, focost[f] / chunks_target);
+        else if (xcd) tf = std::max<int64_t>(64, focost[f] / xcd_chunks);
+        const int32_t qe = vp[fvb[f + 1]];
+        int32_t qb = vp[fvb[f]];
+        int64_t acc = 0;
+        for (int32_t q = qb; q < qe; ++q) {
+          acc += occ_cost[q] + 1;
+          if (acc >= tf || q + 1 == qe) {
+            oc.beg.push_back(qb);
+            oc.end.push_back(q + 1);
+            qb = q + 1;
+            acc = 0;
+          }
+        }
+      }
+      oc.f_first[F] = oc.count();
+      h->och = oc;
+      if (xcd) xcd_order(oc, &oorder);
+    }
   }
   {
     std::vector<int64_t> pre(stored_ids.size() + 1, 0);
@@ -783,12 +886,24 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   h->n_seg = (int32_t)seg_var.size();
   // partial-sum rows of a step, contiguous per formula: its variable chunks,
   // its stored-clause chunks, then its segment chunks
+  // (two-phase: its occurrence chunks, then its stored-clause chunks; the
+  // variable sums write no partial rows)
   const int VC = h->vch.count(), SC = h->sch.count(), GC = h->segch.count(), AC = h->ach.count();
-  std::vector<int32_t> vrow(VC), srow(SC), grow(GC), frow0(F), frow1(F), faa0(F), faa1(F);
+  const int OC = h->och.count();
+  std::vector<int32_t> vrow(VC, 0), srow(SC), grow(GC, 0), orow(OC), frow0(F), frow1(F), faa0(F),
+      faa1(F);
   {
     int32_t row = 0;
     for (int32_t f = 0; f < F; ++f) {
       frow0[f] = row;
+      if (two) {
+        for (int c = h->och.f_first[f]; c < h->och.f_first[f + 1]; ++c) orow[c] = row++;
+        for (int c = h->sch.f_first[f]; c < h->sch.f_first[f + 1]; ++c) srow[c] = row++;
+        frow1[f] = row;
+        faa0[f] = h->ach.f_first[f];
+        faa1[f] = h->ach.f_first[f + 1];
+        continue;
+      }
       for (int c = h->vch.f_first[f]; c < h->vch.f_first[f + 1]; ++c) vrow[c] = row++;
       for (int c = h->sch.f_first[f]; c < h->sch.f_first[f + 1]; ++c) srow[c] = row++;
       for (int c = h->segch.f_first[f]; c < h->segch.f_first[f + 1]; ++c) grow[c] = row++;
@@ -842,6 +957,23 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(vch_row, vrow);
   UP(vch_order, vorder);
   c->n_vorder = (int32_t)vorder.size();
+  if (!vperm.empty()) UP(var_perm, vperm);
+  std::unique_ptr<int32_t[]> own;  // kept until the uploads have completed
+  if (two) {
+    UP(och_beg, c->och.beg);
+    UP(och_end, c->och.end);
+    UP(och_row, orow);
+    UP(och_order, oorder);
+    c->n_oorder = (int32_t)oorder.size();
+    own.reset(new int32_t[(size_t)L + 1]);
+    parallel_for(n, [&](int64_t v0, int64_t v1) {
+      for (int64_t v = v0; v < v1; ++v)
+        for (int32_t q = vp[v]; q < vp[v + 1]; ++q) own[q] = (int32_t)v;
+    });
+    if ((he = c->upload(&c->occ_own, own.get(), (size_t)L, s)) != hipSuccess)
+      return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
+                         std::string("upload slot owners: ") + hipGetErrorString(he));
+  }
   UP(sch_beg, c->sch.beg);
   UP(sch_end, c->sch.end);
   UP(sch_row, srow);
@@ -863,7 +995,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(zero_empty, fnone);
   UP(f_vbeg, fvb);
   UP(f_cbeg, fcb);
-  if (stored > 0) AL(D, (size_t)stored * (size_t)c->ldD);
+  if (two) AL(D, (size_t)std::max<int64_t>(L, 1) * (size_t)c->ldD);  // one row per slot
+  else if (stored > 0) AL(D, (size_t)stored * (size_t)c->ldD);
   AL(xa, (size_t)n * c->ld);
   AL(xb, (size_t)n * c->ld);
   const int64_t rows = std::max<int64_t>(c->step_rows, AC);
@@ -913,7 +1046,7 @@ extern "C" galsat_status galsat_get_info(galsat_handle h, galsat_info* info) {
   info->restarts_per_lane = h->tile.rpl;
   info->var_chunks = h->vch.count() + h->segch.count();
   info->clause_chunks = h->sch.count();
-  info->batched_items = 0;
+  info->two_phase = h->two_phase;
   info->device_bytes = h->device_bytes;
   info->adam_step = h->adam_t;
   return GALSAT_OK;
@@ -962,6 +1095,9 @@ VarPassArgs var_args(const galsat_ctx* h) {
   a.heavy_sbeg = h->heavy_sbeg;
   a.var_formula = h->var_formula;
   a.stream_items = h->stream_items;
+  a.occ_own = h->occ_own;
+  a.var_perm = h->var_perm;
+  a.C = h->D;
   a.D = h->D;
   a.ldD = h->ldD;
   a.loss_part = h->loss_part;
@@ -972,6 +1108,62 @@ VarPassArgs var_args(const galsat_ctx* h) {
   a.b2 = h->opt.beta2;
   a.eps = h->opt.eps;
   return a;
+}
+
+// The two-phase gradient of one restart-tile group (after the clause pass
+// has written the stored clauses' contributions): every recomputed
+// occurrence's contribution, then each whole variable's sum with the
+// epilogue, then the split variables' segment sums and their finish.
+galsat_status two_phase_passes(galsat_ctx* h, VarPassArgs va, Tile t, int mode, int f0, int f1,
+                               hipStream_t s) {
+  const bool all = f0 == 0 && f1 == h->F;
+  {
+    VarPassArgs oa = va;
+    oa.chunk_vbeg = h->och_beg;
+    oa.chunk_vend = h->och_end;
+    oa.chunk_row = h->och_row;
+    oa.chunk_base = h->och.f_first[f0];
+    int blocks = h->och.f_first[f1] - h->och.f_first[f0];
+    oa.chunk_order = nullptr;
+    if (h->n_oorder > 0 && all) {
+      oa.chunk_order = h->och_order;
+      oa.chunk_base = 0;
+      blocks = h->n_oorder;
+    }
+    ProfScope _ps(h, GALSAT_K_OCC_PASS, s);
+    GS_HIP(h, launch_occ_pass(oa, t, blocks, s), "occurrence pass");
+  }
+  {
+    VarPassArgs sa = va;
+    sa.chunk_vbeg = h->vch_beg;
+    sa.chunk_vend = h->vch_end;
+    sa.chunk_base = h->vch.f_first[f0];
+    int blocks = h->vch.f_first[f1] - h->vch.f_first[f0];
+    sa.chunk_order = nullptr;
+    if (h->n_vorder > 0 && all) {
+      sa.chunk_order = h->vch_order;
+      sa.chunk_base = 0;
+      blocks = h->n_vorder;
+    }
+    ProfScope _ps(h, GALSAT_K_VAR_SUM, s);
+    GS_HIP(h, launch_var_sum(sa, mode, t, blocks, s), "variable sum");
+  }
+  const int gc0 = h->segch.f_first[f0], gc1 = h->segch.f_first[f1];
+  if (gc1 > gc0) {
+    VarPassArgs ga = va;
+    ga.chunk_vbeg = h->segch_beg;
+    ga.chunk_vend = h->segch_end;
+    ga.chunk_base = gc0;
+    ga.chunk_order = nullptr;
+    {
+      ProfScope _ps(h, GALSAT_K_VAR_SUM, s);
+      GS_HIP(h, launch_seg_sum(ga, t, gc1 - gc0, s), "segment sum");
+    }
+    ProfScope _ps(h, GALSAT_K_VAR_SUM, s);
+    GS_HIP(h, launch_heavy_finish(va, mode, t, h->heavy_f_first[f0], h->heavy_f_first[f1], s),
+           "split-variable finish");
+  }
+  return GALSAT_OK;
 }
 
 // Gradient passes for formulas [f0, f1) at state x: stored-clause partials,
@@ -1002,6 +1194,7 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
   // the planned group size applies to the planned tile; a fallback tile
   // (unaligned caller buffers) keeps the same restart span per launch
   const int tg = std::max(1, h->tgroup * h->tile.tile() / t.tile());
+  galsat_status st = GALSAT_OK;
   for (int tb = 0; tb < tiles_all; tb += tg) {
     const int tc = std::min(tg, tiles_all - tb);
     if (h->stored > 0 && sc1 > sc0) {
@@ -1028,6 +1221,11 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
     }
     va.tile_base = tb;
     va.tile_count = tc;
+    if (h->two_phase) {
+      st = two_phase_passes(h, va, t, mode, f0, f1, s);
+      if (st != GALSAT_OK) return st;
+      continue;
+    }
     va.chunk_vbeg = h->vch_beg;
     va.chunk_vend = h->vch_end;
     va.chunk_row = h->vch_row;

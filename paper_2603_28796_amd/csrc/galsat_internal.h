@@ -45,6 +45,10 @@ struct VarPassArgs {
   int32_t tile_base;            // first restart tile of this launch
   int32_t tile_count;           // restart tiles of this launch (0: all from tile_base)
   int32_t stream_items;         // 1: walk each slot's variables as one occurrence list
+  const int32_t* occ_own;       // [L] own variable of each slot (two-phase plan)
+  const int32_t* var_perm;      // [n] variable processed as the i-th item of the variable
+                                // chunks (cost-sorted within each chunk), or null: identity
+  float* C;                     // [L][ldD] per-occurrence contributions (two-phase plan)
   const float* x;
   int32_t ldx;
   float* out;                   // next state (update modes) or gradient (grad mode)
@@ -106,6 +110,10 @@ bool plan_cache_lookup(const std::string& key, std::string* plan);
 // Launchers (galsat_kernels.hip).  All return the launch's hipError_t.
 hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s);
 hipError_t launch_var_seg(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
+// Two-phase plan: per-occurrence contributions, then per-variable sums.
+hipError_t launch_occ_pass(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
+hipError_t launch_var_sum(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s);
+hipError_t launch_seg_sum(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
 hipError_t launch_heavy_finish(const VarPassArgs& a, int mode, Tile t, int h0, int h1,
                                hipStream_t s);
 hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int chunks,

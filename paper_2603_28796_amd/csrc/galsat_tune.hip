@@ -123,6 +123,9 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
     krecs = {",krec=8", ",krec=" + std::to_string(kmax)};
   std::vector<std::string> xcd = {""};
   if (prob->num_formulas > 1 && base.schedule != GALSAT_SCHED_PLAIN) xcd = {",xcdc=160", ",xcdc=40"};
+  // narrow restart batches: the single pass against the two-phase gradient
+  std::vector<std::string> twos = {""};
+  if (R <= 64) twos = {",two=0", ",two=1"};
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   float* xs = nullptr;
@@ -133,37 +136,39 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
   double best = 1e300;
   std::string best_plan;
   galsat_status result = GALSAT_OK;
+  std::vector<std::string> plans;
   for (const auto& t : tiles)
     for (const auto& k : krecs)
-      for (const auto& x : xcd) {
-        const std::string plan = t + k + x;
-        galsat_options o = base;
-        o.plan_override = plan.c_str();
-        galsat_handle h = nullptr;
-        galsat_status st = galsat_create(prob, &o, stream, &h);
-        if (st != GALSAT_OK) {
-          if (st == GALSAT_ENOMEM) continue;  // a storing plan may not fit: skip it
-          result = st;
-          break;
-        }
-        (void)hipMemcpyAsync(xs, x0, (size_t)n * ldx * sizeof(float), hipMemcpyDeviceToDevice, s);
-        st = galsat_step(h, xs, ldx, nullptr, 1, nullptr, nullptr, stream);  // warm-up
-        (void)hipEventRecord(e0, s);
-        if (st == GALSAT_OK) st = galsat_step(h, xs, ldx, nullptr, steps, nullptr, nullptr, stream);
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        galsat_destroy(h);
-        if (st != GALSAT_OK) {
-          result = st;
-          break;
-        }
-        if (ms < best) {
-          best = ms;
-          best_plan = plan;
-        }
-      }
+      for (const auto& x : xcd)
+        for (const auto& w : twos) plans.push_back(t + k + x + w);
+  for (const auto& plan : plans) {
+    galsat_options o = base;
+    o.plan_override = plan.c_str();
+    galsat_handle h = nullptr;
+    galsat_status st = galsat_create(prob, &o, stream, &h);
+    if (st != GALSAT_OK) {
+      if (st == GALSAT_ENOMEM) continue;  // a storing plan may not fit: skip it
+      result = st;
+      break;
+    }
+    (void)hipMemcpyAsync(xs, x0, (size_t)n * ldx * sizeof(float), hipMemcpyDeviceToDevice, s);
+    st = galsat_step(h, xs, ldx, nullptr, 1, nullptr, nullptr, stream);  // warm-up
+    (void)hipEventRecord(e0, s);
+    if (st == GALSAT_OK) st = galsat_step(h, xs, ldx, nullptr, steps, nullptr, nullptr, stream);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    galsat_destroy(h);
+    if (st != GALSAT_OK) {
+      result = st;
+      break;
+    }
+    if (ms < best) {
+      best = ms;
+      best_plan = plan;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(xs);

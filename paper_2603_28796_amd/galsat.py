@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libgalsat.so")
 
 OPT = {"sgd": 0, "sgd_clamp": 0, "adam": 1}
 PARTIALS = {"auto": 0, "store": 1, "recompute": 2}
-SCHEDULE = {"auto": 0, "general": 1, "batched": 2, "plain": 3}
+SCHEDULE = {"auto": 0, "general": 1, "plain": 3}
 SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
 
 _P = ctypes.c_void_p
@@ -70,7 +70,7 @@ class _Info(ctypes.Structure):
         ("restarts", _I32), ("max_clause_len", _I32), ("recompute_max_len", _I32),
         ("stored_lits", ctypes.c_int64), ("schedule", _I32), ("lanes_per_item", _I32),
         ("restarts_per_lane", _I32), ("var_chunks", _I32), ("clause_chunks", _I32),
-        ("batched_items", _I32), ("device_bytes", ctypes.c_size_t), ("adam_step", _I32),
+        ("two_phase", _I32), ("device_bytes", ctypes.c_size_t), ("adam_step", _I32),
     ]
 
 
@@ -85,11 +85,12 @@ EXPORTS = ("galsat_default_options", "galsat_create", "galsat_destroy", "galsat_
            "galsat_status_string", "galsat_last_error")
 
 KERNEL_KINDS = ("var_pass", "clause_pass", "finalize", "copy", "pack", "count", "select",
-                "batched")
+                "occ_pass", "var_sum")
 
 
 class _KernelTimes(ctypes.Structure):
-    _fields_ = [("launches", _I32 * 8), ("total_ms", ctypes.c_double * 8)]
+    _fields_ = [("launches", _I32 * len(KERNEL_KINDS)),
+                ("total_ms", ctypes.c_double * len(KERNEL_KINDS))]
 
 _lib = None
 

@@ -25,6 +25,21 @@ def test_header_and_binding_agree():
     assert _declared() == sorted(G.EXPORTS)
 
 
+def test_kernel_kinds_and_info_layout_match_header():
+    text = open(HEADER).read()
+    kinds = int(re.search(r"GALSAT_K_KINDS\s*=\s*(\d+)", text).group(1))
+    assert kinds == len(G.KERNEL_KINDS)
+    body = text[:text.index("} galsat_info;")]
+    body = body[body.rindex("typedef struct {") + len("typedef struct {"):]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            names += [w.strip() for w in decl.split(None, 1)[1].split(",")]
+    assert names == [k for k, _ in G._Info._fields_]
+
+
 def test_library_exports_every_declared_symbol():
     lib = G.load_library()
     for name in _declared():

@@ -99,6 +99,96 @@ def test_tile_overrides(lpi, rpl, stream):
     assert torch.equal(g1, g0)
 
 
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("R", [3, 16, 40, 64])
+@pytest.mark.parametrize("partials", ["auto", "store"])
+def test_two_phase_matches_single_pass(case, R, partials):
+    """The two-phase gradient (occurrence pass + variable sums) forms the same
+    contributions and sums them in the same order as the single pass, so
+    gradients, states and counts are bitwise equal; the loss partial sums
+    are grouped differently (allclose)."""
+    say(f"[two-phase] case={case} R={R} partials={partials}")
+    cnf = CASES[case]()
+    kw = dict(partials=partials, lr=0.1)
+    if partials == "auto":
+        kw["recompute_max_len"] = 4
+    two = Problem(cnf, R, plan_override="two=1", **kw)
+    one = Problem(cnf, R, plan_override="two=0", **kw)
+    assert two.info()["two_phase"] == 1 and one.info()["two_phase"] == 0
+    x = _x0(cnf.n, R, seed=40 + R)
+    l2, g2 = two.loss_grad(x)
+    l1, g1 = one.loss_grad(x)
+    torch.cuda.synchronize()
+    assert torch.equal(g2, g1)
+    assert torch.allclose(l2, l1, rtol=1e-6, atol=1e-30)
+    xa, xb = x.clone(), x.clone()
+    la, ua = two.step(xa, 3, trace=True)
+    lb, ub = one.step(xb, 3, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb)
+    assert torch.equal(ua, ub)
+    assert torch.allclose(la, lb, rtol=1e-6, atol=1e-30)
+    parity_at(two, cnf, xa, f"two-phase {case}/R={R}/{partials}")
+
+
+@pytest.mark.parametrize("lpi", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("rpl", [1, 2, 4])
+def test_two_phase_tiles(lpi, rpl):
+    say(f"[two-phase tiles] lpi={lpi} rpl={rpl}")
+    cnf = CASES["long_mix"]() if lpi % 8 else CASES["batch"]()
+    R = 40
+    prob = Problem(cnf, R, partials="auto", recompute_max_len=4,
+                   plan_override=f"lpi={lpi},rpl={rpl},two=1")
+    parity_at(prob, cnf, _x0(cnf.n, R, 7), f"two-phase lpi={lpi} rpl={rpl}")
+
+
+@pytest.mark.parametrize("plan", ["dsort=1", "csort=1", "dsort=1,csort=1,two=1",
+                                  "dsort=1,two=0,lpi=4,rpl=4"])
+def test_sorted_item_orders(plan):
+    """Cost-sorted variable items and length-sorted stored clauses change
+    only which lanes take which item: gradients, states and counts are
+    bitwise those of the index order."""
+    say(f"[sorted] {plan}")
+    for case in ("long_mix", "batch", "edge"):
+        cnf = CASES[case]()
+        R = 16
+        ref_plan = ("two=1" if "two=1" in plan else "two=0") + ",dsort=0,csort=0"
+        if "lpi" in plan:
+            ref_plan += ",lpi=4,rpl=4"
+        a = Problem(cnf, R, recompute_max_len=4, plan_override=plan)
+        b = Problem(cnf, R, recompute_max_len=4, plan_override=ref_plan)
+        x = _x0(cnf.n, R, 31)
+        la, ga = a.loss_grad(x)
+        lb, gb = b.loss_grad(x)
+        xa, xb = x.clone(), x.clone()
+        ta, ua = a.step(xa, 3, trace=True)
+        tb, ub = b.step(xb, 3, trace=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ga, gb), case
+        assert torch.allclose(la, lb, rtol=1e-6, atol=1e-30), case
+        assert torch.equal(xa, xb) and torch.equal(ua, ub), case
+        parity_at(a, cnf, xa, f"{plan} {case}")
+
+
+def test_two_phase_adam_and_upstream():
+    say("[two-phase adam]")
+    cnf = CASES["batch"]()
+    R = 8
+    up = torch.randn(cnf.F, R, device="cuda")
+    two = Problem(cnf, R, plan_override="two=1")
+    parity_at(two, cnf, _x0(cnf.n, R, 22), "two-phase upstream", upstream=up)
+    pa = Problem(cnf, R, optimizer="adam", lr=0.05, plan_override="two=1")
+    pb = Problem(cnf, R, optimizer="adam", lr=0.05, plan_override="two=0")
+    x = _x0(cnf.n, R, 23)
+    xa, xb = x.clone(), x.clone()
+    sa, sb = pa.new_opt_state(xa), pb.new_opt_state(xb)
+    pa.step(xa, 4, opt_state=sa)
+    pb.step(xb, 4, opt_state=sb)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb)
+    assert torch.equal(sa, sb)
+
+
 def test_unaligned_and_padded_state():
     say("[layout] padded and odd row strides")
     cnf = CASES["planted300"]()
