@@ -7,11 +7,13 @@ library next to this file.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgalsat.so")
-SOURCES = ["galsat_kernels.hip", "galsat_host.hip", "galsat_tseitin.hip", "galsat_tune.hip"]
+SOURCES = ["galsat_varpass.hip", "galsat_twophase.hip", "galsat_clause.hip", "galsat_modes.hip",
+           "galsat_host.hip", "galsat_tseitin.hip", "galsat_tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -23,19 +25,26 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    jobs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
-            continue
+            raise FileNotFoundError(path)
         obj = os.path.join(build_dir, src + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", path, "-o", obj]
+        jobs.append(([HIPCC] + FLAGS + ["-c", path, "-o", obj], obj))
+
+    def compile_one(job):
+        cmd, obj = job
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+        return obj
+
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        objs = list(pool.map(compile_one, jobs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:

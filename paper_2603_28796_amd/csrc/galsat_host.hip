@@ -136,6 +136,8 @@ struct galsat_ctx {
   Chunks vch, sch, ach;  // var chunks, stored-clause chunks, all-clause chunks
   Chunks segch;          // chunks of segments of split variables
   Chunks och;            // occurrence-range chunks of the two-phase plan
+  Chunks wch;            // chunks of the wave-per-clause stored clauses
+  Chunks hch;            // chunks of the short stored clauses
   std::vector<int32_t> heavy_f_first;  // [F+1] split variables of each formula
   int32_t n_heavy = 0, n_seg = 0, step_rows = 0;
 
@@ -151,6 +153,10 @@ struct galsat_ctx {
   int32_t* occ_own = nullptr;  // [L] variable of each variable-major slot (two-phase)
   int32_t* var_perm = nullptr;  // cost-sorted item order of the variable chunks, or null
   int32_t *sch_beg = nullptr, *sch_end = nullptr, *sch_row = nullptr;
+  int32_t *wave_ids = nullptr;  // stored clauses of the wave-per-clause pass
+  int32_t *wch_beg = nullptr, *wch_end = nullptr, *wch_row = nullptr;
+  int32_t *short_ids = nullptr;  // stored clauses of the short-clause pass
+  int32_t *hch_beg = nullptr, *hch_end = nullptr, *hch_row = nullptr;
   int32_t *segch_beg = nullptr, *segch_end = nullptr, *segch_row = nullptr;
   int32_t *ach_beg = nullptr, *ach_end = nullptr;
   int32_t *seg_var = nullptr, *seg_q0 = nullptr, *seg_q1 = nullptr;
@@ -347,9 +353,11 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // Parses "key=value,key=value" plan overrides: lpi, rpl, krec, tg, xcdc
 // (chunks per formula of multi-formula launches; 0 turns the XCD order off),
 // stream (1: streaming variable pass), two (1: two-phase gradient), dsort
-// (1: cost-sorted variable items), csort (1: length-sorted stored clauses).
+// (1: cost-sorted variable items), csort (1: length-sorted stored clauses),
+// wave (0: no wave-per-clause pass), short (0: no short-clause pass).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
-                    int* stream_items, int* two_phase, int* dsort, int* csort) {
+                    int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
+                    int* short_clauses) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -370,6 +378,8 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "two") *two_phase = v;
       else if (k == "dsort") *dsort = v;
       else if (k == "csort") *csort = v;
+      else if (k == "wave") *wave = v;
+      else if (k == "short") *short_clauses = v;
     }
     pos = comma + 1;
   }
@@ -551,9 +561,9 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
 
   // ---- plan: which clauses recompute their partials in the variable pass
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
-  int dsort_o = -1, csort_o = -1;
+  int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
-                 &dsort_o, &csort_o);
+                 &dsort_o, &csort_o, &wave_o, &short_o);
   const bool csort = csort_o != 0;
   const int64_t xcd_chunks = xcdc_o >= 0 ? xcdc_o : kXcdChunks;
   int32_t krec;
@@ -604,6 +614,15 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     int tg = (int)std::max<int64_t>(1, kCacheBudgetBytes / tile_bytes);
     if (tg_o > 0) tg = tg_o;
     h->tgroup = std::min(tg, tiles_all);
+  }
+  // The two-phase plan writes a contribution row for every occurrence
+  // anyway: by default every clause stores its partials (each literal's row
+  // gathered once, by the clause passes) and nothing is recomputed per
+  // occurrence.
+  {
+    const bool krec_given = opt.recompute_max_len > 0 ||
+                            (krec_o >= -1 && opt.plan_override && std::strstr(opt.plan_override, "krec="));
+    if (h->two_phase && opt.partials == GALSAT_PARTIALS_AUTO && !krec_given) krec = 0;
   }
   auto count_stored = [&](int32_t kr) {
     std::atomic<int64_t> c{0};
@@ -697,6 +716,34 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       });
   }
   f_sbeg[F] = (int64_t)stored_ids.size();
+  // Stored clauses by length: at most kShortClauseMax literals to the
+  // short-clause pass, up to the wave-per-clause pass's limit for the tile
+  // to that pass, the rest to the sweeping clause pass.
+  std::vector<int32_t> wave_ids, short_ids;
+  std::vector<int64_t> f_wbeg((size_t)F + 1, 0), f_hbeg((size_t)F + 1, 0);
+  {
+    const int kw_max = wave_o != 0 ? wave_clause_kmax(h->tile) : 0;
+    const int ks_max = short_o != 0 ? kShortClauseMax : 0;
+    std::vector<int32_t> keep;
+    keep.reserve(stored_ids.size());
+    std::vector<int64_t> f_kbeg((size_t)F + 1, 0);
+    for (int32_t f = 0; f < F; ++f) {
+      f_kbeg[f] = (int64_t)keep.size();
+      f_wbeg[f] = (int64_t)wave_ids.size();
+      f_hbeg[f] = (int64_t)short_ids.size();
+      for (int64_t i = f_sbeg[f]; i < f_sbeg[f + 1]; ++i) {
+        const int32_t t = stored_ids[(size_t)i], k = cp[t + 1] - cp[t];
+        if (k <= ks_max) short_ids.push_back(t);
+        else if (k <= kw_max) wave_ids.push_back(t);
+        else keep.push_back(t);
+      }
+    }
+    f_kbeg[F] = (int64_t)keep.size();
+    f_wbeg[F] = (int64_t)wave_ids.size();
+    f_hbeg[F] = (int64_t)short_ids.size();
+    stored_ids.swap(keep);
+    f_sbeg.swap(f_kbeg);
+  }
 
   // ---- chunks of balanced cost.  The cost of a variable is its number of
   // gathered rows per restart; a chunk (one workgroup) gets about
@@ -831,7 +878,10 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     heavy_f_first[F] = (int32_t)heavy.size();
     h->vch = vc;
     h->segch = sc;
-    if (two) {
+    // (no occurrence chunks when every occurrence's partial is stored; the
+    // per-formula index stays valid and empty)
+    h->och.f_first.assign((size_t)F + 1, 0);
+    if (two && stored < L) {
       // occurrence chunks of the two-phase plan: ranges of variable-major
       // slots of about equal gather cost (+1 per slot for its row store)
       Chunks oc;
@@ -875,6 +925,18 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     h->sch = make_chunks(F, f_sbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target));
   }
   {
+    std::vector<int64_t> pre(wave_ids.size() + 1, 0);
+    for (size_t i = 0; i < wave_ids.size(); ++i)
+      pre[i + 1] = pre[i] + 1 + (cp[wave_ids[i] + 1] - cp[wave_ids[i]]);
+    h->wch = make_chunks(F, f_wbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target));
+  }
+  {
+    std::vector<int64_t> pre(short_ids.size() + 1, 0);
+    for (size_t i = 0; i < short_ids.size(); ++i)
+      pre[i + 1] = pre[i] + 1 + (cp[short_ids[i] + 1] - cp[short_ids[i]]);
+    h->hch = make_chunks(F, f_hbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target));
+  }
+  {
     std::vector<int64_t> pre((size_t)m + 1, 0), fb(fcb.begin(), fcb.end());
     for (int32_t t = 0; t < m; ++t) pre[t + 1] = pre[t] + 1 + (cp[t + 1] - cp[t]);
     h->ach = make_chunks(F, fb, pre, std::max<int64_t>(256, pre[m] / chunks_target));
@@ -890,8 +952,9 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // variable sums write no partial rows)
   const int VC = h->vch.count(), SC = h->sch.count(), GC = h->segch.count(), AC = h->ach.count();
   const int OC = h->och.count();
-  std::vector<int32_t> vrow(VC, 0), srow(SC), grow(GC, 0), orow(OC), frow0(F), frow1(F), faa0(F),
-      faa1(F);
+  const int WC = h->wch.count(), HC = h->hch.count();
+  std::vector<int32_t> vrow(VC, 0), srow(SC), wrow(WC), hrow(HC), grow(GC, 0), orow(OC), frow0(F),
+      frow1(F), faa0(F), faa1(F);
   {
     int32_t row = 0;
     for (int32_t f = 0; f < F; ++f) {
@@ -899,6 +962,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       if (two) {
         for (int c = h->och.f_first[f]; c < h->och.f_first[f + 1]; ++c) orow[c] = row++;
         for (int c = h->sch.f_first[f]; c < h->sch.f_first[f + 1]; ++c) srow[c] = row++;
+        for (int c = h->wch.f_first[f]; c < h->wch.f_first[f + 1]; ++c) wrow[c] = row++;
+        for (int c = h->hch.f_first[f]; c < h->hch.f_first[f + 1]; ++c) hrow[c] = row++;
         frow1[f] = row;
         faa0[f] = h->ach.f_first[f];
         faa1[f] = h->ach.f_first[f + 1];
@@ -906,6 +971,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       }
       for (int c = h->vch.f_first[f]; c < h->vch.f_first[f + 1]; ++c) vrow[c] = row++;
       for (int c = h->sch.f_first[f]; c < h->sch.f_first[f + 1]; ++c) srow[c] = row++;
+      for (int c = h->wch.f_first[f]; c < h->wch.f_first[f + 1]; ++c) wrow[c] = row++;
+      for (int c = h->hch.f_first[f]; c < h->hch.f_first[f + 1]; ++c) hrow[c] = row++;
       for (int c = h->segch.f_first[f]; c < h->segch.f_first[f + 1]; ++c) grow[c] = row++;
       frow1[f] = row;
       faa0[f] = h->ach.f_first[f];
@@ -977,6 +1044,14 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(sch_beg, c->sch.beg);
   UP(sch_end, c->sch.end);
   UP(sch_row, srow);
+  UP(wave_ids, wave_ids);
+  UP(wch_beg, c->wch.beg);
+  UP(wch_end, c->wch.end);
+  UP(wch_row, wrow);
+  UP(short_ids, short_ids);
+  UP(hch_beg, c->hch.beg);
+  UP(hch_end, c->hch.end);
+  UP(hch_row, hrow);
   UP(segch_beg, c->segch.beg);
   UP(segch_end, c->segch.end);
   UP(segch_row, grow);
@@ -1218,6 +1293,58 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
       ca.R = h->R;
       ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
       GS_HIP(h, launch_clause_pass(ca, true, t, sc1 - sc0, s), "clause pass");
+    }
+    const int wc0 = h->wch.f_first[f0], wc1 = h->wch.f_first[f1];
+    if (wc1 > wc0) {
+      ClausePassArgs ca{};
+      ca.clause_ptr = h->clause_ptr;
+      ca.clause_lits = h->clause_lits;
+      ca.lit_dslot = h->lit_dslot;
+      ca.clause_ids = h->wave_ids;
+      ca.chunk_cbeg = h->wch_beg;
+      ca.chunk_cend = h->wch_end;
+      ca.chunk_row = h->wch_row;
+      ca.chunk_base = wc0;
+      ca.tile_base = tb;
+      ca.tile_count = tc;
+      ca.x = x;
+      ca.ldx = ldx;
+      ca.D = h->D;
+      ca.ldD = h->ldD;
+      ca.loss_part = h->loss_part;
+      ca.unsat_part = h->unsat_part;
+      ca.R = h->R;
+      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
+      // the clause lengths were routed for the planned tile; a fallback
+      // tile (unaligned caller buffers) runs them through the sweeping pass
+      if (t.lpi == h->tile.lpi && t.rpl == h->tile.rpl) {
+        GS_HIP(h, launch_wave_clause(ca, t, wc1 - wc0, s), "wave clause pass");
+      } else {
+        GS_HIP(h, launch_clause_pass(ca, true, t, wc1 - wc0, s), "clause pass");
+      }
+    }
+    const int hc0 = h->hch.f_first[f0], hc1 = h->hch.f_first[f1];
+    if (hc1 > hc0) {
+      ClausePassArgs ca{};
+      ca.clause_ptr = h->clause_ptr;
+      ca.clause_lits = h->clause_lits;
+      ca.lit_dslot = h->lit_dslot;
+      ca.clause_ids = h->short_ids;
+      ca.chunk_cbeg = h->hch_beg;
+      ca.chunk_cend = h->hch_end;
+      ca.chunk_row = h->hch_row;
+      ca.chunk_base = hc0;
+      ca.tile_base = tb;
+      ca.tile_count = tc;
+      ca.x = x;
+      ca.ldx = ldx;
+      ca.D = h->D;
+      ca.ldD = h->ldD;
+      ca.loss_part = h->loss_part;
+      ca.unsat_part = h->unsat_part;
+      ca.R = h->R;
+      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
+      GS_HIP(h, launch_short_clause(ca, t, hc1 - hc0, s), "short clause pass");
     }
     va.tile_base = tb;
     va.tile_count = tc;

@@ -103,11 +103,23 @@ struct FinalizeArgs {
 
 enum VarMode { kModeSGD = 0, kModeAdam = 1, kModeGrad = 2 };
 
+// Short-clause pass: stored clauses of at most this many literals, one
+// item per clause with its partials formed in registers.
+constexpr int kShortClauseMax = 8;
+
+// Wave-per-clause pass: chunks of G = 64 / lpi literals held in registers,
+// and the longest clause it takes for a tile (0: the tile does not use it).
+constexpr int wave_clause_chunks(int lpi) { return lpi == 4 ? 13 : 16; }
+inline int wave_clause_kmax(Tile t) {
+  return (t.lpi == 4 || t.lpi == 8 || t.lpi == 16) ? (64 / t.lpi) * wave_clause_chunks(t.lpi) : 0;
+}
+
 // Plan cache of the autotuner (galsat_tune.hip).
 std::string plan_key(const galsat_problem* prob);
 bool plan_cache_lookup(const std::string& key, std::string* plan);
 
-// Launchers (galsat_kernels.hip).  All return the launch's hipError_t.
+// Launchers (galsat_varpass.hip, galsat_twophase.hip, galsat_clause.hip,
+// galsat_modes.hip).  All return the launch's hipError_t.
 hipError_t launch_var_pass(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s);
 hipError_t launch_var_seg(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
 // Two-phase plan: per-occurrence contributions, then per-variable sums.
@@ -116,6 +128,8 @@ hipError_t launch_var_sum(const VarPassArgs& a, int mode, Tile t, int chunks, hi
 hipError_t launch_seg_sum(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
 hipError_t launch_heavy_finish(const VarPassArgs& a, int mode, Tile t, int h0, int h1,
                                hipStream_t s);
+hipError_t launch_wave_clause(const ClausePassArgs& a, Tile t, int chunks, hipStream_t s);
+hipError_t launch_short_clause(const ClausePassArgs& a, Tile t, int chunks, hipStream_t s);
 hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int chunks,
                               hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, int F, hipStream_t s);

@@ -144,3 +144,37 @@ def test_rejects_bad_sizes(small):
 def test_python_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(RuntimeError, match="not found"):
         G.load_library(str(tmp_path / "missing.so"))
+
+
+@pytest.mark.parametrize("plan", ["", "two=1", "two=0", "two=1,short=0", "two=1,wave=0",
+                                  "lpi=4,rpl=4", "lpi=16,rpl=1,two=1", "stream=1", "two=1,krec=4"])
+@pytest.mark.parametrize("partials", [0, 1, 2])
+def test_planning_completes_for_every_plan(plan, partials):
+    """galsat_create's host planning (records, chunk tables, partial-sum row
+    layout) for uneven batches with empty and long clauses: without a GPU it
+    must get as far as the first upload (GALSAT_EDEVICE); with one, succeed."""
+    fs = [I.planted_ksat(30 + 7 * i, 4 * (30 + 7 * i), 3, seed=500 + i) for i in range(5)]
+    fs.append(I.from_clauses([[]], n=1))
+    fs.append(I.generate(I.spec(2, k0=3, ka=20, kb=80, p0=0.8, var_kind=1, zipf_s=1.2),
+                         21, [400], [500], "long"))
+    cnf = I.concat(fs, name="plan")
+    lib = G.load_library()
+    arrs = {k: np.ascontiguousarray(getattr(cnf, k), dtype=np.int32) for k in
+            ("formula_var_begin", "formula_clause_begin", "clause_ptr", "clause_lits", "var_ptr",
+             "var_occ")}
+    for R in (1, 16, 40):
+        prob = G._Problem(cnf.F, arrs["formula_var_begin"].ctypes.data,
+                          arrs["formula_clause_begin"].ctypes.data, cnf.n, cnf.m, cnf.L,
+                          arrs["clause_ptr"].ctypes.data, arrs["clause_lits"].ctypes.data,
+                          arrs["var_ptr"].ctypes.data, arrs["var_occ"].ctypes.data, R, 0)
+        opt = G._Options()
+        lib.galsat_default_options(ctypes.byref(opt))
+        opt.partials = partials
+        keep = plan.encode() if plan else None
+        opt.plan_override = keep
+        h = ctypes.c_void_p()
+        st = lib.galsat_create(ctypes.byref(prob), ctypes.byref(opt), None, ctypes.byref(h))
+        if st == 0:
+            lib.galsat_destroy(h)
+        else:
+            assert st == -3, (R, lib.galsat_last_error(None))

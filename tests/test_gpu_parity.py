@@ -113,7 +113,10 @@ def test_two_phase_matches_single_pass(case, R, partials):
     if partials == "auto":
         kw["recompute_max_len"] = 4
     two = Problem(cnf, R, plan_override="two=1", **kw)
-    one = Problem(cnf, R, plan_override="two=0", **kw)
+    inf = two.info()
+    # same tile for both, so the wave-per-clause pass groups literals alike
+    tile = f"lpi={inf['lanes_per_item']},rpl={inf['restarts_per_lane']}"
+    one = Problem(cnf, R, plan_override="two=0," + tile, **kw)
     assert two.info()["two_phase"] == 1 and one.info()["two_phase"] == 0
     x = _x0(cnf.n, R, seed=40 + R)
     l2, g2 = two.loss_grad(x)
@@ -152,10 +155,11 @@ def test_sorted_item_orders(plan):
     for case in ("long_mix", "batch", "edge"):
         cnf = CASES[case]()
         R = 16
-        ref_plan = ("two=1" if "two=1" in plan else "two=0") + ",dsort=0,csort=0"
-        if "lpi" in plan:
-            ref_plan += ",lpi=4,rpl=4"
         a = Problem(cnf, R, recompute_max_len=4, plan_override=plan)
+        inf = a.info()
+        # the same plan in index order: same tile and gradient form
+        ref_plan = (f"two={inf['two_phase']},lpi={inf['lanes_per_item']},"
+                    f"rpl={inf['restarts_per_lane']},dsort=0,csort=0")
         b = Problem(cnf, R, recompute_max_len=4, plan_override=ref_plan)
         x = _x0(cnf.n, R, 31)
         la, ga = a.loss_grad(x)
@@ -170,6 +174,60 @@ def test_sorted_item_orders(plan):
         parity_at(a, cnf, xa, f"{plan} {case}")
 
 
+@pytest.mark.parametrize("plan", ["lpi=4,rpl=4", "lpi=4,rpl=1", "lpi=8,rpl=2", "lpi=16,rpl=1",
+                                  "lpi=4,rpl=4,two=1", "lpi=8,rpl=4,two=0"])
+@pytest.mark.parametrize("partials", ["auto", "store"])
+def test_wave_clause_pass(plan, partials):
+    """Stored clauses of G..KMAX literals (G = 64 / lanes per item) take the
+    wave-per-clause pass: parity with the oracle, and agreement with the
+    sweeping clause pass to the gradient tolerance (the products associate
+    differently, so not bitwise)."""
+    say(f"[wave] {plan} {partials}")
+    cnf = CASES["long_mix"]()
+    R = 16
+    kw = dict(partials=partials, lr=0.1)
+    if partials == "auto":
+        kw["recompute_max_len"] = 8
+    a = Problem(cnf, R, plan_override=plan, **kw)
+    b = Problem(cnf, R, plan_override=plan + ",wave=0", **kw)
+    x = _x0(cnf.n, R, 51)
+    parity_at(a, cnf, x, f"wave {plan}")
+    la, ga = a.loss_grad(x)
+    lb, gb = b.loss_grad(x)
+    torch.cuda.synchronize()
+    assert torch.allclose(la, lb, rtol=2e-6, atol=1e-30)
+    _, g_ref, A = oracle.grad(cnf, to_oracle(x, R), with_abs=True)
+    scale = torch.from_numpy((np.abs(g_ref) + A).T.copy()).to(ga.device)[:, :R]
+    assert torch.all((ga[:, :R] - gb[:, :R]).abs().double() <= 2e-5 * scale + 1e-30)
+    # a few fused steps stay within the per-step tolerance of each other
+    xa = x.clone()
+    la, ua = a.step(xa, 2, trace=True)
+    torch.cuda.synchronize()
+    parity_at(a, cnf, xa, f"wave {plan} after 2 steps")
+
+
+@pytest.mark.parametrize("case", ["mixed20k", "long_mix", "tseitin3", "edge", "batch"])
+@pytest.mark.parametrize("plan", ["two=1", "two=1,short=0", "two=1,wave=0,short=0",
+                                  "two=1,lpi=16,rpl=1", "two=0,krec=-1"])
+def test_clause_centric_partials(case, plan):
+    """Every clause storing its partials (the two-phase default): short
+    clauses through the register pass, long ones through the wave-per-clause
+    pass, the rest through the sweeping pass; parity with the oracle and
+    agreement between the routes to the gradient tolerance."""
+    say(f"[clause-centric] {case} {plan}")
+    cnf = CASES[case]()
+    R = 16
+    a = Problem(cnf, R, plan_override=plan)
+    if plan.startswith("two=1"):
+        assert a.info()["stored_lits"] == cnf.L  # nothing recomputed per occurrence
+    x = _x0(cnf.n, R, 61)
+    parity_at(a, cnf, x, f"{case} {plan}")
+    xa = x.clone()
+    a.step(xa, 2)
+    torch.cuda.synchronize()
+    parity_at(a, cnf, xa, f"{case} {plan} after 2 steps")
+
+
 def test_two_phase_adam_and_upstream():
     say("[two-phase adam]")
     cnf = CASES["batch"]()
@@ -177,8 +235,10 @@ def test_two_phase_adam_and_upstream():
     up = torch.randn(cnf.F, R, device="cuda")
     two = Problem(cnf, R, plan_override="two=1")
     parity_at(two, cnf, _x0(cnf.n, R, 22), "two-phase upstream", upstream=up)
+    # the two-phase default stores every clause's partials: the single pass
+    # with the same partials sums the same values in the same order
     pa = Problem(cnf, R, optimizer="adam", lr=0.05, plan_override="two=1")
-    pb = Problem(cnf, R, optimizer="adam", lr=0.05, plan_override="two=0")
+    pb = Problem(cnf, R, optimizer="adam", lr=0.05, plan_override="two=0,krec=0")
     x = _x0(cnf.n, R, 23)
     xa, xb = x.clone(), x.clone()
     sa, sb = pa.new_opt_state(xa), pb.new_opt_state(xb)
