@@ -29,9 +29,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "fwd+bwd literal-evals/s & % HBM peak; batched vs plain, 1e-5 rel vs FP64"
 # the sources that define the variable pass (its traffic figure is only
-# reported while these are unchanged since the counters were taken)
-KERNEL_SRC = [os.path.join(ROOT, "paper_2603_28796_amd", "csrc", f)
-              for f in ("galsat_device.h", "galsat_internal.h", "galsat_varpass.hip")]
+# reported while these are unchanged since the counters were taken): the
+# device helpers, the pass itself and its argument struct
+CSRC = os.path.join(ROOT, "paper_2603_28796_amd", "csrc")
+KERNEL_SRC = [os.path.join(CSRC, f) for f in ("galsat_device.h", "galsat_varpass.hip")]
 
 
 def log(*a):
@@ -43,6 +44,9 @@ def kernel_source_hash() -> str:
     for path in KERNEL_SRC:
         with open(path, "rb") as fh:
             h.update(fh.read())
+    text = open(os.path.join(CSRC, "galsat_internal.h")).read()
+    start = text.index("struct VarPassArgs {")
+    h.update(text[start:text.index("};", start)].encode())
     return h.hexdigest()[:16]
 
 
