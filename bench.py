@@ -160,6 +160,9 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay the step loop from a hipGraph")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the batched vs one-formula-at-a-time comparison (0: skip)")
+    ap.add_argument("--tseitin", type=int, default=0,
+                    help="run the workload after chain normalization to this clause width "
+                         "(Eq. 6-7); also reports the unsat count on the original clauses")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -178,6 +181,13 @@ def main():
     w = I.WORKLOADS[args.workload]
     t0 = time.perf_counter()
     cnf = w.make()
+    original = None
+    if args.tseitin:
+        from paper_2603_28796_amd.galsat import tseitin
+        original = cnf
+        cnf = tseitin(cnf, args.tseitin)
+        log(f"[bench] width-{args.tseitin} normalization: n {original.n} -> {cnf.n}, "
+            f"m {original.m} -> {cnf.m}, L {original.L} -> {cnf.L}")
     log(f"[bench] workload {w.key}: n={cnf.n} m={cnf.m} L={cnf.L} F={cnf.F} R={w.restarts} "
         f"(generated in {time.perf_counter() - t0:.1f} s)")
     R = w.restarts
@@ -213,6 +223,19 @@ def main():
     value = R * cnf.L * K / (ms / 1e3)
     log(f"[bench] timed {K} steps: {ms:.2f} ms ({ms / K:.4f} ms/step), {value:.4e} lit-evals/s; "
         f"min unsat {int(unsat.min())}, final mean loss {float(lt[K - 1].mean()):.3f}")
+    normalized = None
+    if original is not None:
+        # the original variables keep their ids: round them and count the
+        # original clauses they leave unsatisfied
+        orig_prob = Problem(original, R, lr=w.lr)
+        u0, _, _ = orig_prob.round_check(x[:original.n])
+        torch.cuda.synchronize()
+        normalized = {"width": args.tseitin, "original_n": original.n, "original_m": original.m,
+                      "original_L": original.L, "min_unsat_original": int(u0.min()),
+                      "min_unsat_normalized": int(unsat.min()),
+                      "original_lit_evals_per_s": R * original.L * K / (ms / 1e3)}
+        log(f"[bench] normalized run: {normalized}")
+        orig_prob.close()
 
     roofline = None
     kernels = None
@@ -262,13 +285,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.key, "description": w.description, "n": cnf.n, "m": cnf.m,
+        "config": {"workload": w.key + (f"/width{args.tseitin}" if args.tseitin else ""),
+                   "description": w.description, "n": cnf.n, "m": cnf.m,
                    "L": cnf.L, "formulas": cnf.F, "restarts": R, "lr": w.lr, "partials": partials,
                    "lanes_per_item": info["lanes_per_item"],
                    "restarts_per_lane": info["restarts_per_lane"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_vs_plain": batch,
+        "normalized": normalized,
         "kernel_ms": {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 5)}
                       for k, v in (kernels or {}).items()},
     }
