@@ -146,6 +146,47 @@ def batched_vs_plain(steps: int):
     return out
 
 
+def gumbel_and_handoff(cnf, R, steps: int):
+    """The paper's own optimizer loop on the same instance (straight-through
+    Gumbel-softmax, Adam lr 0.5, tau 1), then the hand-off to the CPU stage:
+    100 candidates (Eq. 8), the top 0.05 % confident variables of each as
+    unit literals (Eq. 9-10) and the 7 least confident of the selected
+    restart as branching variables (Lemma 1).  Event-timed on the current
+    stream, inputs resident in HBM."""
+    import torch
+
+    from paper_2603_28796_amd import inputs as I
+    from paper_2603_28796_amd.galsat import Problem
+
+    prob = Problem(cnf, R, optimizer="adam", lr=0.5)
+    x0 = prob.init_state(I.SEED_BASE + 6)
+    d = (x0 * 2.0 - 1.0).contiguous()  # initial logit differences in [-1, 1)
+    opt = prob.new_opt_state(d)
+    prob.gumbel_step(d, 2, opt_state=opt, seed=7, step0=0)  # warm-up
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    e[0].record()
+    lt, ut = prob.gumbel_step(d, steps, opt_state=opt, seed=7, step0=2, trace=True)
+    e[1].record()
+    best = ut[-1].to(torch.int64).argmin(dim=1).to(torch.int32)  # fewest unsat, first index
+    e[2].record()
+    assign, conf = prob.candidates(d, best, num=100, seed=8, tau=1.0)
+    off_u, units = prob.select_vars(conf, highest=True, frac=0.0005, min_count=1)
+    conf1 = prob.confidence(d, best, tau=1.0)
+    off_b, branch = prob.select_vars(conf1, highest=False, frac=0.0, min_count=7)
+    e[3].record()
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1])
+    out = {"optimizer": "adam", "lr": 0.5, "tau": 1.0, "steps": steps, "restarts": R,
+           "ms_per_step": ms / steps, "lit_evals_per_s": R * cnf.L * steps / (ms / 1e3),
+           "min_unsat_first_step": int(ut[0].min()), "min_unsat_last_step": int(ut[-1].min()),
+           "handoff": {"candidates": 100, "ms": e[2].elapsed_time(e[3]),
+                       "unit_literals_per_candidate": int(off_u[-1]),
+                       "branching_vars": int(off_b[-1])}}
+    prob.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +201,8 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay the step loop from a hipGraph")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the batched vs one-formula-at-a-time comparison (0: skip)")
+    ap.add_argument("--gumbel-steps", type=int, default=50,
+                    help="steps of the straight-through Gumbel loop + hand-off timing (0: skip)")
     ap.add_argument("--tseitin", type=int, default=0,
                     help="run the workload after chain normalization to this clause width "
                          "(Eq. 6-7); also reports the unsat count on the original clauses")
@@ -262,6 +305,12 @@ def main():
                         "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_ms, 5),
                         "launches_per_step": per_step}
 
+    gumbel = None
+    if args.gumbel_steps > 0 and not args.tseitin:
+        prob.close()  # free the SGD handle's workspace first
+        gumbel = gumbel_and_handoff(cnf, R, args.gumbel_steps)
+        log(f"[bench] gumbel-ST + hand-off: {gumbel}")
+
     batch = None
     if args.batch_steps > 0:
         batch = batched_vs_plain(args.batch_steps)
@@ -294,6 +343,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_vs_plain": batch,
         "normalized": normalized,
+        "gumbel_st": gumbel,
         "kernel_ms": {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 5)}
                       for k, v in (kernels or {}).items()},
     }
