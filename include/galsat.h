@@ -137,7 +137,11 @@ typedef struct {
                               4), krec recompute threshold, tg restart tiles per launch,
                               xcdc chunks per formula of the XCD-aware order (0: off),
                               stream (1: streaming variable pass), two (1: two-phase
-                              gradient, 0: single pass; default: the plan's choice) */
+                              gradient, 0: single pass), dsort / csort (cost-sorted
+                              variable items / length-sorted stored clauses, 0 or 1),
+                              wave / short (0: no wave-per-clause / short-clause pass),
+                              xseq (one formula: chunks of the XCD-contiguous order,
+                              0: off).  Keys left out take the plan's own choice. */
 } galsat_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -300,7 +304,8 @@ typedef struct {
   int32_t lanes_per_item;       /* restarts lanes of one variable or clause */
   int32_t restarts_per_lane;
   int32_t var_chunks, clause_chunks;
-  int32_t two_phase;            /* 1: the gradient runs as occurrence pass + variable sum */
+  int32_t two_phase;            /* 1: two-phase gradient (clause passes + variable sums) */
+  int32_t xseq_chunks;          /* chunks of the XCD-contiguous order of one formula, 0: off */
   size_t device_bytes;          /* device memory held by the handle */
   int32_t adam_step;
 } galsat_info;

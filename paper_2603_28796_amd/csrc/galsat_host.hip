@@ -30,6 +30,10 @@ thread_local std::string g_create_error;
 constexpr int kDefaultRecomputeMaxLen = 8;
 constexpr int kTargetBlocks = 2048;  // blocks per general-pass launch (256 CUs x 8)
 constexpr double kTwoPhaseSkew = 2.0;  // degree skew above which narrow batches go two-phase
+// XCD-contiguous order of one formula: chunk count (about five waves of
+// resident workgroups per XCD) and the id window that counts as local.
+constexpr int64_t kXseqChunks = 6144;
+constexpr int32_t kLocalWindow = 4096;
 constexpr int64_t kCacheBudgetBytes = 256ll << 20;  // state rows one launch may gather from
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 constexpr int64_t kXcdChunks = 160;                 // workgroups resident on one XCD (about)
@@ -126,6 +130,7 @@ struct galsat_ctx {
   int tgroup = 1;    // restart tiles per launch of a gradient pass
   int stream_items = 0;  // streaming variable pass
   int two_phase = 0;     // occurrence pass + variable sum instead of the single pass
+  int32_t xseq = 0;      // chunks of the XCD-contiguous order (0: off)
   int32_t ld = 0;    // internal state row stride (floats)
   int64_t ldD = 0;
   int adam_t = 0;
@@ -354,10 +359,11 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // (chunks per formula of multi-formula launches; 0 turns the XCD order off),
 // stream (1: streaming variable pass), two (1: two-phase gradient), dsort
 // (1: cost-sorted variable items), csort (1: length-sorted stored clauses),
-// wave (0: no wave-per-clause pass), short (0: no short-clause pass).
+// wave (0: no wave-per-clause pass), short (0: no short-clause pass), xseq
+// (one formula: about this many chunks in an XCD-contiguous order).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
                     int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
-                    int* short_clauses) {
+                    int* short_clauses, int* xseq) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -380,6 +386,7 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "csort") *csort = v;
       else if (k == "wave") *wave = v;
       else if (k == "short") *short_clauses = v;
+      else if (k == "xseq") *xseq = v;
     }
     pos = comma + 1;
   }
@@ -561,9 +568,9 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
 
   // ---- plan: which clauses recompute their partials in the variable pass
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
-  int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1;
+  int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
-                 &dsort_o, &csort_o, &wave_o, &short_o);
+                 &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o);
   const bool csort = csort_o != 0;
   const int64_t xcd_chunks = xcdc_o >= 0 ? xcdc_o : kXcdChunks;
   int32_t krec;
@@ -763,8 +770,29 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     });
     int64_t total = 0;
     for (int32_t v = 0; v < n; ++v) total += vcost[v];
-    const int64_t target = std::max<int64_t>(64, total / chunks_target);
+    int64_t target = std::max<int64_t>(64, total / chunks_target);
     const int64_t item_cap = std::max<int64_t>(64, target / ipb);
+    // XCD-contiguous order (one formula): many small chunks, each XCD taking
+    // a contiguous run of them, so the workgroups resident on an XCD cover a
+    // narrow range of variable ids and share the rows they gather in its L2
+    // when the numbering has locality.
+    // By default for a single formula whose clauses mostly join nearby
+    // variable ids (measured on a sample: a literal within kLocalWindow ids
+    // of its clause's first literal).
+    int64_t xseq_chunks = xseq_o;
+    if (xseq_o < 0 && F == 1 && m > 0) {
+      int64_t near = 0, pairs = 0;
+      const int64_t stride = std::max<int64_t>(1, m / 200000);
+      for (int64_t t = 0; t < m; t += stride)
+        for (int32_t i = cp[t] + 1; i < cp[t + 1]; ++i) {
+          near += std::abs((cl[i] >> 1) - (cl[cp[t]] >> 1)) < kLocalWindow ? 1 : 0;
+          ++pairs;
+        }
+      xseq_chunks = (pairs > 0 && near * 2 > pairs && n > 64 * kLocalWindow) ? kXseqChunks : 0;
+    }
+    h->xseq = xseq_chunks > 0 ? (int32_t)xseq_chunks : 0;
+    const bool xseq = F == 1 && xseq_chunks > 0;
+    if (xseq) target = std::max<int64_t>(1, total / xseq_chunks);
     Chunks vc, sc;
     vc.f_first.assign((size_t)F + 1, 0);
     sc.f_first.assign((size_t)F + 1, 0);
@@ -864,6 +892,12 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     };
     const bool xcd = F > 1 && !per_formula && xcd_chunks > 0;
     if (xcd) xcd_order(vc, &vorder);
+    if (xseq) {
+      const int32_t C = vc.count(), per = (C + kXcds - 1) / kXcds;
+      vorder.assign((size_t)per * kXcds, -1);
+      for (int x = 0; x < kXcds; ++x)
+        for (int32_t i = 0; i < per && x * per + i < C; ++i) vorder[(size_t)i * kXcds + x] = x * per + i;
+    }
     if (dsort) {
       // item order within each variable chunk: costliest first, so the
       // variables sharing a wave have similar occurrence counts
@@ -1122,6 +1156,7 @@ extern "C" galsat_status galsat_get_info(galsat_handle h, galsat_info* info) {
   info->var_chunks = h->vch.count() + h->segch.count();
   info->clause_chunks = h->sch.count();
   info->two_phase = h->two_phase;
+  info->xseq_chunks = h->xseq;
   info->device_bytes = h->device_bytes;
   info->adam_step = h->adam_t;
   return GALSAT_OK;

@@ -70,7 +70,7 @@ class _Info(ctypes.Structure):
         ("restarts", _I32), ("max_clause_len", _I32), ("recompute_max_len", _I32),
         ("stored_lits", ctypes.c_int64), ("schedule", _I32), ("lanes_per_item", _I32),
         ("restarts_per_lane", _I32), ("var_chunks", _I32), ("clause_chunks", _I32),
-        ("two_phase", _I32), ("device_bytes", ctypes.c_size_t), ("adam_step", _I32),
+        ("two_phase", _I32), ("xseq_chunks", _I32), ("device_bytes", ctypes.c_size_t), ("adam_step", _I32),
     ]
 
 

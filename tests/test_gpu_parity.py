@@ -228,6 +228,32 @@ def test_clause_centric_partials(case, plan):
     parity_at(a, cnf, xa, f"{case} {plan} after 2 steps")
 
 
+@pytest.mark.parametrize("case", ["mixed20k", "planted300", "long_mix", "tseitin3"])
+@pytest.mark.parametrize("chunks", [8, 64, 1000])
+def test_xcd_contiguous_order(case, chunks):
+    """One formula in many small chunks dealt to the XCDs in contiguous runs:
+    only which workgroup takes which variables changes, so gradients,
+    states and counts are bitwise those of the default order."""
+    say(f"[xseq] {case} {chunks}")
+    cnf = CASES[case]()
+    for R in (16, 100):
+        a = Problem(cnf, R, plan_override=f"xseq={chunks}")
+        inf = a.info()
+        assert inf["xseq_chunks"] == chunks
+        tile = f"lpi={inf['lanes_per_item']},rpl={inf['restarts_per_lane']},two={inf['two_phase']}"
+        b = Problem(cnf, R, plan_override=tile + ",xseq=0")
+        x = _x0(cnf.n, R, 71)
+        la, ga = a.loss_grad(x)
+        lb, gb = b.loss_grad(x)
+        xa, xb = x.clone(), x.clone()
+        ta, ua = a.step(xa, 3, trace=True)
+        tb, ub = b.step(xb, 3, trace=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ga, gb) and torch.equal(xa, xb) and torch.equal(ua, ub)
+        assert torch.allclose(la, lb, rtol=1e-6, atol=1e-30)
+        parity_at(a, cnf, xa, f"xseq {case} {chunks} R={R}")
+
+
 def test_two_phase_adam_and_upstream():
     say("[two-phase adam]")
     cnf = CASES["batch"]()
