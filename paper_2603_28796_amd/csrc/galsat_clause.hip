@@ -128,9 +128,11 @@ __global__ __launch_bounds__(kBlock) void k_clause_pass(ClausePassArgs a) {
 
 // ---------------------------------------------- short-clause partials
 //
-// Stored clauses of at most KS literals, one item (LPI lanes) per clause:
-// the clause's rows are gathered once into registers, the exclusive prefix
-// and suffix products formed there, and every literal's partial
+// Stored clauses of at most KS literals, one item (LPI lanes) per clause,
+// read from the class's packed table (codes and D rows, -1 marking unused
+// positions): the clause's rows are gathered once into registers, the
+// exclusive prefix and suffix products formed there, and every literal's
+// partial
 //   slope_j * prefix_j * suffix_j
 // written to its row of D.  One gather and one store per literal.
 template <int LPI, int RPL, int KS>
@@ -150,17 +152,22 @@ __global__ __launch_bounds__(kBlock) void k_short_clause(ClausePassArgs a) {
   for (int j = 0; j < RPL; ++j) { lsum[j] = 0.0; usum[j] = 0; }
 
   for (int c0 = cb + slot; c0 < ce; c0 += IPB) {
-    const int t = uniform<LPI>(a.clause_ids ? ldc(a.clause_ids, c0) : c0);
-    const int s = ldc(a.clause_ptr, t), k = ldc(a.clause_ptr, t + 1) - s;  // 1 <= k <= KS
+    // the class's packed table: the clause's codes and D rows side by side,
+    // so its row gathers depend on one table load only
+    const int32_t* pk = a.packed + (int64_t)uniform<LPI>(c0) * 2 * KS;
+    int code[KS], drow[KS];
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      code[u] = ldc(pk, u);
+      drow[u] = ldc(pk, KS + u);
+    }
     float f[KS][RPL];
-    int code[KS];
     bool any_true[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; ++j) any_true[j] = false;
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
-      const bool in = u < k;
-      code[u] = in ? ldc(a.clause_lits, s + u) : 0;
+      const bool in = drow[u] >= 0;
       float y[RPL];
       if (in) {
         load_row<RPL>(a.x + (int64_t)(code[u] >> 1) * a.ldx + rc, y);
@@ -202,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_short_clause(ClausePassArgs a) {
         dv[j] = slope * (pre[u][j] * suf[j]);
         suf[j] *= f[u][j];
       }
-      if (active && u < k) store_row<RPL>(a.D + (int64_t)ldc(a.lit_dslot, s + u) * a.ldD + r0, dv);
+      if (active && drow[u] >= 0) store_row<RPL>(a.D + (int64_t)drow[u] * a.ldD + r0, dv);
     }
   }
   block_partials<LPI, RPL>(lsum, usum, a.chunk_row ? ldc(a.chunk_row, chunk) : chunk, tile, a.R,
@@ -241,9 +248,17 @@ __global__ __launch_bounds__(kBlock) void k_wave_clause(ClausePassArgs a) {
 #pragma unroll
   for (int j = 0; j < RPL; ++j) { lsum[j] = 0.0; usum[j] = 0; }
 
-  for (int i = cb + wave; i < ce; i += WPB) {
+  // the next clause's header is loaded while the current one is processed
+  auto header = [&](int i, int* s, int* k) {
     const int t = __builtin_amdgcn_readfirstlane(a.clause_ids ? ldc(a.clause_ids, i) : i);
-    const int s = ldc(a.clause_ptr, t), k = ldc(a.clause_ptr, t + 1) - s;
+    *s = ldc(a.clause_ptr, t);
+    *k = ldc(a.clause_ptr, t + 1) - *s;
+  };
+  int s_next = 0, k_next = 0;
+  if (cb + wave < ce) header(cb + wave, &s_next, &k_next);
+  for (int i = cb + wave; i < ce; i += WPB) {
+    const int s = s_next, k = k_next;
+    if (i + WPB < ce) header(i + WPB, &s_next, &k_next);
     const int m = (k + G - 1) / G;  // run length (the plan keeps m <= MAXC)
     const int lb = grp * m;         // first literal of this group's run
     float f[MAXC][RPL];
@@ -521,14 +536,18 @@ hipError_t clause_pass_lpi(const ClausePassArgs& a, bool write_d, Tile t, int ch
 }
 }  // namespace
 
-hipError_t launch_short_clause(const ClausePassArgs& a, Tile t, int chunks, hipStream_t s) {
+hipError_t launch_short_clause(const ClausePassArgs& a, Tile t, int ks, int chunks, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
+  if (ks != 4 && ks != kShortClauseMax) return hipErrorInvalidValue;
   const int tiles = launch_tiles(a, t);
   dim3 grid(chunks, tiles), block(kBlock);
   switch (t.lpi * 8 + t.rpl) {
 #define GALSAT_SHORT_CASE(L, P)                                                                 \
   case L * 8 + P:                                                                               \
-    hipLaunchKernelGGL((k_short_clause<L, P, kShortClauseMax>), grid, block, 0, s, a);          \
+    if (ks == 4)                                                                                \
+      hipLaunchKernelGGL((k_short_clause<L, P, 4>), grid, block, 0, s, a);                      \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_short_clause<L, P, kShortClauseMax>), grid, block, 0, s, a);        \
     break;
     GALSAT_SHORT_CASE(4, 1)
     GALSAT_SHORT_CASE(4, 2)
@@ -551,15 +570,19 @@ hipError_t launch_short_clause(const ClausePassArgs& a, Tile t, int chunks, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_wave_clause(const ClausePassArgs& a, Tile t, int chunks, hipStream_t s) {
+hipError_t launch_wave_clause(const ClausePassArgs& a, Tile t, int maxc, int chunks, hipStream_t s) {
   if (chunks <= 0) return hipSuccess;
   if (wave_clause_kmax(t) <= 0) return hipErrorInvalidValue;
+  if (maxc != kWaveClauseSmallChunks && maxc != wave_clause_chunks(t.lpi)) return hipErrorInvalidValue;
   const int tiles = launch_tiles(a, t);
   dim3 grid(chunks, tiles), block(kBlock);
   switch (t.lpi * 8 + t.rpl) {
 #define GALSAT_WAVE_CASE(L, P)                                                                  \
   case L * 8 + P:                                                                               \
-    hipLaunchKernelGGL((k_wave_clause<L, P, wave_clause_chunks(L)>), grid, block, 0, s, a);     \
+    if (maxc == kWaveClauseSmallChunks)                                                         \
+      hipLaunchKernelGGL((k_wave_clause<L, P, kWaveClauseSmallChunks>), grid, block, 0, s, a);  \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_wave_clause<L, P, wave_clause_chunks(L)>), grid, block, 0, s, a);   \
     break;
     GALSAT_WAVE_CASE(4, 1)
     GALSAT_WAVE_CASE(4, 2)

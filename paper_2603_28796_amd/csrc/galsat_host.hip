@@ -33,6 +33,7 @@ constexpr double kTwoPhaseSkew = 2.0;  // degree skew above which narrow batches
 // XCD-contiguous order of one formula: chunk count (about five waves of
 // resident workgroups per XCD) and the id window that counts as local.
 constexpr int64_t kXseqChunks = 6144;
+constexpr int kClassShort = 0, kClassWave = 1;  // passes of the stored-clause classes
 constexpr int32_t kLocalWindow = 4096;
 constexpr int64_t kCacheBudgetBytes = 256ll << 20;  // state rows one launch may gather from
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
@@ -141,8 +142,6 @@ struct galsat_ctx {
   Chunks vch, sch, ach;  // var chunks, stored-clause chunks, all-clause chunks
   Chunks segch;          // chunks of segments of split variables
   Chunks och;            // occurrence-range chunks of the two-phase plan
-  Chunks wch;            // chunks of the wave-per-clause stored clauses
-  Chunks hch;            // chunks of the short stored clauses
   std::vector<int32_t> heavy_f_first;  // [F+1] split variables of each formula
   int32_t n_heavy = 0, n_seg = 0, step_rows = 0;
 
@@ -158,10 +157,16 @@ struct galsat_ctx {
   int32_t* occ_own = nullptr;  // [L] variable of each variable-major slot (two-phase)
   int32_t* var_perm = nullptr;  // cost-sorted item order of the variable chunks, or null
   int32_t *sch_beg = nullptr, *sch_end = nullptr, *sch_row = nullptr;
-  int32_t *wave_ids = nullptr;  // stored clauses of the wave-per-clause pass
-  int32_t *wch_beg = nullptr, *wch_end = nullptr, *wch_row = nullptr;
-  int32_t *short_ids = nullptr;  // stored clauses of the short-clause pass
-  int32_t *hch_beg = nullptr, *hch_end = nullptr, *hch_row = nullptr;
+  // Stored clauses by length class, each class with its own pass instance
+  // (register-sized for its longest clause) and chunk table.
+  struct ClauseClass {
+    int kind = 0;   // kClassShort or kClassWave
+    int param = 0;  // literals (short) or chunks of G literals (wave) held in registers
+    Chunks ch;
+    int32_t *ids = nullptr, *beg = nullptr, *end = nullptr, *row = nullptr;
+    int32_t* packed = nullptr;  // short classes: [clauses][2][param] codes, then D rows
+  };
+  std::vector<ClauseClass> cls;
   int32_t *segch_beg = nullptr, *segch_end = nullptr, *segch_row = nullptr;
   int32_t *ach_beg = nullptr, *ach_end = nullptr;
   int32_t *seg_var = nullptr, *seg_q0 = nullptr, *seg_q1 = nullptr;
@@ -723,31 +728,46 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       });
   }
   f_sbeg[F] = (int64_t)stored_ids.size();
-  // Stored clauses by length: at most kShortClauseMax literals to the
-  // short-clause pass, up to the wave-per-clause pass's limit for the tile
-  // to that pass, the rest to the sweeping clause pass.
-  std::vector<int32_t> wave_ids, short_ids;
-  std::vector<int64_t> f_wbeg((size_t)F + 1, 0), f_hbeg((size_t)F + 1, 0);
+  // Stored clauses by length class, shortest first: at most 4 and at most
+  // kShortClauseMax literals to the short-clause pass, then up to two
+  // wave-per-clause classes (kWaveClauseSmallChunks and the tile's maximum
+  // chunks of G = 64 / lanes-per-item literals), the rest to the sweeping
+  // clause pass.  Each class's kernel holds only what its longest clause
+  // needs in registers.
+  struct Route { int kind, param, kmax; };
+  std::vector<Route> routes;
+  if (short_o != 0) {
+    routes.push_back({kClassShort, 4, 4});
+    routes.push_back({kClassShort, kShortClauseMax, kShortClauseMax});
+  }
   {
     const int kw_max = wave_o != 0 ? wave_clause_kmax(h->tile) : 0;
-    const int ks_max = short_o != 0 ? kShortClauseMax : 0;
+    if (kw_max > 0) {
+      const int G = 64 / h->tile.lpi;
+      if (kWaveClauseSmallChunks * G < kw_max)
+        routes.push_back({kClassWave, kWaveClauseSmallChunks, kWaveClauseSmallChunks * G});
+      routes.push_back({kClassWave, wave_clause_chunks(h->tile.lpi), kw_max});
+    }
+  }
+  const int NCL = (int)routes.size();
+  std::vector<std::vector<int32_t>> cls_ids((size_t)NCL);
+  std::vector<std::vector<int64_t>> cls_fbeg((size_t)NCL, std::vector<int64_t>((size_t)F + 1, 0));
+  {
     std::vector<int32_t> keep;
     keep.reserve(stored_ids.size());
     std::vector<int64_t> f_kbeg((size_t)F + 1, 0);
-    for (int32_t f = 0; f < F; ++f) {
+    for (int32_t f = 0; f <= F; ++f) {
       f_kbeg[f] = (int64_t)keep.size();
-      f_wbeg[f] = (int64_t)wave_ids.size();
-      f_hbeg[f] = (int64_t)short_ids.size();
+      for (int c = 0; c < NCL; ++c) cls_fbeg[c][f] = (int64_t)cls_ids[c].size();
+      if (f == F) break;
       for (int64_t i = f_sbeg[f]; i < f_sbeg[f + 1]; ++i) {
         const int32_t t = stored_ids[(size_t)i], k = cp[t + 1] - cp[t];
-        if (k <= ks_max) short_ids.push_back(t);
-        else if (k <= kw_max) wave_ids.push_back(t);
+        int c = 0;
+        while (c < NCL && k > routes[c].kmax) ++c;
+        if (c < NCL) cls_ids[c].push_back(t);
         else keep.push_back(t);
       }
     }
-    f_kbeg[F] = (int64_t)keep.size();
-    f_wbeg[F] = (int64_t)wave_ids.size();
-    f_hbeg[F] = (int64_t)short_ids.size();
     stored_ids.swap(keep);
     f_sbeg.swap(f_kbeg);
   }
@@ -958,17 +978,14 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       pre[i + 1] = pre[i] + 1 + 2 * (cp[stored_ids[i] + 1] - cp[stored_ids[i]]);
     h->sch = make_chunks(F, f_sbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target));
   }
-  {
-    std::vector<int64_t> pre(wave_ids.size() + 1, 0);
-    for (size_t i = 0; i < wave_ids.size(); ++i)
-      pre[i + 1] = pre[i] + 1 + (cp[wave_ids[i] + 1] - cp[wave_ids[i]]);
-    h->wch = make_chunks(F, f_wbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target));
-  }
-  {
-    std::vector<int64_t> pre(short_ids.size() + 1, 0);
-    for (size_t i = 0; i < short_ids.size(); ++i)
-      pre[i + 1] = pre[i] + 1 + (cp[short_ids[i] + 1] - cp[short_ids[i]]);
-    h->hch = make_chunks(F, f_hbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target));
+  h->cls.resize((size_t)NCL);
+  for (int c = 0; c < NCL; ++c) {
+    const std::vector<int32_t>& ids = cls_ids[c];
+    std::vector<int64_t> pre(ids.size() + 1, 0);
+    for (size_t i = 0; i < ids.size(); ++i) pre[i + 1] = pre[i] + 1 + (cp[ids[i] + 1] - cp[ids[i]]);
+    h->cls[c].kind = routes[c].kind;
+    h->cls[c].param = routes[c].param;
+    h->cls[c].ch = make_chunks(F, cls_fbeg[c], pre, std::max<int64_t>(64, pre.back() / chunks_target));
   }
   {
     std::vector<int64_t> pre((size_t)m + 1, 0), fb(fcb.begin(), fcb.end());
@@ -986,9 +1003,14 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // variable sums write no partial rows)
   const int VC = h->vch.count(), SC = h->sch.count(), GC = h->segch.count(), AC = h->ach.count();
   const int OC = h->och.count();
-  const int WC = h->wch.count(), HC = h->hch.count();
-  std::vector<int32_t> vrow(VC, 0), srow(SC), wrow(WC), hrow(HC), grow(GC, 0), orow(OC), frow0(F),
-      frow1(F), faa0(F), faa1(F);
+  std::vector<int32_t> vrow(VC, 0), srow(SC), grow(GC, 0), orow(OC), frow0(F), frow1(F), faa0(F),
+      faa1(F);
+  std::vector<std::vector<int32_t>> crow((size_t)NCL);
+  for (int c = 0; c < NCL; ++c) crow[c].assign((size_t)h->cls[c].ch.count(), 0);
+  auto class_rows = [&](int32_t f, int32_t* row) {
+    for (int c = 0; c < NCL; ++c)
+      for (int k = h->cls[c].ch.f_first[f]; k < h->cls[c].ch.f_first[f + 1]; ++k) crow[c][k] = (*row)++;
+  };
   {
     int32_t row = 0;
     for (int32_t f = 0; f < F; ++f) {
@@ -996,8 +1018,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       if (two) {
         for (int c = h->och.f_first[f]; c < h->och.f_first[f + 1]; ++c) orow[c] = row++;
         for (int c = h->sch.f_first[f]; c < h->sch.f_first[f + 1]; ++c) srow[c] = row++;
-        for (int c = h->wch.f_first[f]; c < h->wch.f_first[f + 1]; ++c) wrow[c] = row++;
-        for (int c = h->hch.f_first[f]; c < h->hch.f_first[f + 1]; ++c) hrow[c] = row++;
+        class_rows(f, &row);
         frow1[f] = row;
         faa0[f] = h->ach.f_first[f];
         faa1[f] = h->ach.f_first[f + 1];
@@ -1005,8 +1026,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       }
       for (int c = h->vch.f_first[f]; c < h->vch.f_first[f + 1]; ++c) vrow[c] = row++;
       for (int c = h->sch.f_first[f]; c < h->sch.f_first[f + 1]; ++c) srow[c] = row++;
-      for (int c = h->wch.f_first[f]; c < h->wch.f_first[f + 1]; ++c) wrow[c] = row++;
-      for (int c = h->hch.f_first[f]; c < h->hch.f_first[f + 1]; ++c) hrow[c] = row++;
+      class_rows(f, &row);
       for (int c = h->segch.f_first[f]; c < h->segch.f_first[f + 1]; ++c) grow[c] = row++;
       frow1[f] = row;
       faa0[f] = h->ach.f_first[f];
@@ -1078,14 +1098,37 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(sch_beg, c->sch.beg);
   UP(sch_end, c->sch.end);
   UP(sch_row, srow);
-  UP(wave_ids, wave_ids);
-  UP(wch_beg, c->wch.beg);
-  UP(wch_end, c->wch.end);
-  UP(wch_row, wrow);
-  UP(short_ids, short_ids);
-  UP(hch_beg, c->hch.beg);
-  UP(hch_end, c->hch.end);
-  UP(hch_row, hrow);
+  std::vector<std::vector<int32_t>> cls_packed((size_t)NCL);
+  for (int k = 0; k < NCL; ++k) {
+    if (routes[k].kind != kClassShort) continue;
+    const int KS = routes[k].param;
+    const std::vector<int32_t>& ids = cls_ids[k];
+    std::vector<int32_t>& pk = cls_packed[k];
+    pk.assign(ids.size() * 2 * KS, 0);
+    parallel_for((int64_t)ids.size(), [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        const int32_t t = ids[(size_t)i], kk = cp[t + 1] - cp[t];
+        int32_t* e = pk.data() + i * 2 * KS;
+        for (int u = 0; u < KS; ++u) {
+          e[u] = u < kk ? cl[cp[t] + u] : 0;
+          e[KS + u] = u < kk ? lit_dslot[cp[t] + u] : -1;
+        }
+      }
+    });
+  }
+  for (int k = 0; k < NCL; ++k) {
+    galsat_ctx::ClauseClass& cc = c->cls[k];
+    if (!cls_packed[k].empty() &&
+        (he = c->upload(&cc.packed, cls_packed[k].data(), cls_packed[k].size(), s)) != hipSuccess)
+      return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
+                         std::string("upload packed clauses: ") + hipGetErrorString(he));
+    if ((he = c->upload(&cc.ids, cls_ids[k].data(), cls_ids[k].size(), s)) != hipSuccess ||
+        (he = c->upload(&cc.beg, cc.ch.beg.data(), cc.ch.beg.size(), s)) != hipSuccess ||
+        (he = c->upload(&cc.end, cc.ch.end.data(), cc.ch.end.size(), s)) != hipSuccess ||
+        (he = c->upload(&cc.row, crow[k].data(), crow[k].size(), s)) != hipSuccess)
+      return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
+                         std::string("upload clause classes: ") + hipGetErrorString(he));
+  }
   UP(segch_beg, c->segch.beg);
   UP(segch_end, c->segch.end);
   UP(segch_row, grow);
@@ -1155,6 +1198,7 @@ extern "C" galsat_status galsat_get_info(galsat_handle h, galsat_info* info) {
   info->restarts_per_lane = h->tile.rpl;
   info->var_chunks = h->vch.count() + h->segch.count();
   info->clause_chunks = h->sch.count();
+  for (const galsat_ctx::ClauseClass& cc : h->cls) info->clause_chunks += cc.ch.count();
   info->two_phase = h->two_phase;
   info->xseq_chunks = h->xseq;
   info->device_bytes = h->device_bytes;
@@ -1329,17 +1373,19 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
       ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
       GS_HIP(h, launch_clause_pass(ca, true, t, sc1 - sc0, s), "clause pass");
     }
-    const int wc0 = h->wch.f_first[f0], wc1 = h->wch.f_first[f1];
-    if (wc1 > wc0) {
+    for (const galsat_ctx::ClauseClass& cc : h->cls) {
+      const int c0 = cc.ch.f_first[f0], c1 = cc.ch.f_first[f1];
+      if (c1 <= c0) continue;
       ClausePassArgs ca{};
       ca.clause_ptr = h->clause_ptr;
       ca.clause_lits = h->clause_lits;
       ca.lit_dslot = h->lit_dslot;
-      ca.clause_ids = h->wave_ids;
-      ca.chunk_cbeg = h->wch_beg;
-      ca.chunk_cend = h->wch_end;
-      ca.chunk_row = h->wch_row;
-      ca.chunk_base = wc0;
+      ca.clause_ids = cc.ids;
+      ca.packed = cc.packed;
+      ca.chunk_cbeg = cc.beg;
+      ca.chunk_cend = cc.end;
+      ca.chunk_row = cc.row;
+      ca.chunk_base = c0;
       ca.tile_base = tb;
       ca.tile_count = tc;
       ca.x = x;
@@ -1350,36 +1396,15 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
       ca.unsat_part = h->unsat_part;
       ca.R = h->R;
       ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
-      // the clause lengths were routed for the planned tile; a fallback
-      // tile (unaligned caller buffers) runs them through the sweeping pass
-      if (t.lpi == h->tile.lpi && t.rpl == h->tile.rpl) {
-        GS_HIP(h, launch_wave_clause(ca, t, wc1 - wc0, s), "wave clause pass");
+      if (cc.kind == kClassShort) {
+        GS_HIP(h, launch_short_clause(ca, t, cc.param, c1 - c0, s), "short clause pass");
+      } else if (t.lpi == h->tile.lpi && t.rpl == h->tile.rpl) {
+        GS_HIP(h, launch_wave_clause(ca, t, cc.param, c1 - c0, s), "wave clause pass");
       } else {
-        GS_HIP(h, launch_clause_pass(ca, true, t, wc1 - wc0, s), "clause pass");
+        // the classes were routed for the planned tile; a fallback tile
+        // (unaligned caller buffers) runs them through the sweeping pass
+        GS_HIP(h, launch_clause_pass(ca, true, t, c1 - c0, s), "clause pass");
       }
-    }
-    const int hc0 = h->hch.f_first[f0], hc1 = h->hch.f_first[f1];
-    if (hc1 > hc0) {
-      ClausePassArgs ca{};
-      ca.clause_ptr = h->clause_ptr;
-      ca.clause_lits = h->clause_lits;
-      ca.lit_dslot = h->lit_dslot;
-      ca.clause_ids = h->short_ids;
-      ca.chunk_cbeg = h->hch_beg;
-      ca.chunk_cend = h->hch_end;
-      ca.chunk_row = h->hch_row;
-      ca.chunk_base = hc0;
-      ca.tile_base = tb;
-      ca.tile_count = tc;
-      ca.x = x;
-      ca.ldx = ldx;
-      ca.D = h->D;
-      ca.ldD = h->ldD;
-      ca.loss_part = h->loss_part;
-      ca.unsat_part = h->unsat_part;
-      ca.R = h->R;
-      ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
-      GS_HIP(h, launch_short_clause(ca, t, hc1 - hc0, s), "short clause pass");
     }
     va.tile_base = tb;
     va.tile_count = tc;

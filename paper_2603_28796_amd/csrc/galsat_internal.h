@@ -74,6 +74,8 @@ struct ClausePassArgs {
   const int32_t* clause_lits;
   const int32_t* lit_dslot;     // [L] stored row of each literal position
   const int32_t* clause_ids;    // [list] clause ids, or null for identity
+  const int32_t* packed;        // short-clause classes: [list][2][KS] literal codes, then
+                                // their D rows (-1 past the clause's end), or null
   const int32_t* chunk_cbeg;    // [chunks] range in the clause list
   const int32_t* chunk_cend;
   const int32_t* chunk_row;     // [chunks] partial-sum row, or null for row = chunk
@@ -110,6 +112,7 @@ constexpr int kShortClauseMax = 8;
 // Wave-per-clause pass: chunks of G = 64 / lpi literals held in registers,
 // and the longest clause it takes for a tile (0: the tile does not use it).
 constexpr int wave_clause_chunks(int lpi) { return lpi == 4 ? 13 : 16; }
+constexpr int kWaveClauseSmallChunks = 8;  // a second, lighter instance for shorter clauses
 inline int wave_clause_kmax(Tile t) {
   return (t.lpi == 4 || t.lpi == 8 || t.lpi == 16) ? (64 / t.lpi) * wave_clause_chunks(t.lpi) : 0;
 }
@@ -128,8 +131,10 @@ hipError_t launch_var_sum(const VarPassArgs& a, int mode, Tile t, int chunks, hi
 hipError_t launch_seg_sum(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
 hipError_t launch_heavy_finish(const VarPassArgs& a, int mode, Tile t, int h0, int h1,
                                hipStream_t s);
-hipError_t launch_wave_clause(const ClausePassArgs& a, Tile t, int chunks, hipStream_t s);
-hipError_t launch_short_clause(const ClausePassArgs& a, Tile t, int chunks, hipStream_t s);
+// ks: 4 or kShortClauseMax literals; maxc: kWaveClauseSmallChunks or
+// wave_clause_chunks(t.lpi) chunks of G literals.
+hipError_t launch_wave_clause(const ClausePassArgs& a, Tile t, int maxc, int chunks, hipStream_t s);
+hipError_t launch_short_clause(const ClausePassArgs& a, Tile t, int ks, int chunks, hipStream_t s);
 hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int chunks,
                               hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, int F, hipStream_t s);
