@@ -128,6 +128,8 @@ def batched_vs_plain(steps: int):
         lt = torch.empty((steps, cnf.F, R), dtype=torch.float32, device="cuda")
         ut = torch.empty((steps, cnf.F, R), dtype=torch.int32, device="cuda")
         prob.step(x, 1, loss_trace=lt[:1], unsat_trace=ut[:1], trace=True)  # warm-up
+        torch.cuda.synchronize()
+        log(f"[bench] {name}: warm-up step done")
         x = x0.clone()
         if graph:
             prob.prepare(x, steps, loss_trace=lt, unsat_trace=ut)

@@ -211,10 +211,11 @@ galsat_status galsat_step_prepare(galsat_handle h, float* x, int32_t ldx, float*
  * theta0 with these gradients; the state kept is d, which moves by twice
  * theta1's step (SGD: d -= 2 lr g1; Adam: theta0's moments are the exact
  * negatives of theta1's, so opt_state [2][n][ldd] holds theta1's m and v).
- * No clamp.  Noise for global step t (= step0 + k) is drawn from a
- * counter-based generator:
- *   g_j = -log(-log(u_j)), u_j = ((h_j >> 40) + 0.5) * 2^-24,
- *   h_j = M(seed ^ M(c_j ^ M(t + 0x632be59bd9b4e019))), c_j = v * 2^32 + 2r + j,
+ * No clamp.  The noise difference for global step t (= step0 + k) is drawn
+ * from a counter-based generator; g1 - g0 of independent Gumbel(0,1) draws
+ * is standard logistic, so l is drawn directly from one uniform:
+ *   l = log(u / (1 - u)), u = ((h >> 40) + 0.5) * 2^-24,
+ *   h = M(seed ^ M(c ^ M(t + 0x632be59bd9b4e019))), c = v * 2^32 + r,
  * M the SplitMix64 output mix, evaluated in FP64 and rounded to FP32 once;
  * or, when `noise` is not NULL, read from it ([steps][n][ldd] FP32 l values).
  *   d            device FP32 [n][ldd], updated in place

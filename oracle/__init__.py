@@ -230,7 +230,8 @@ def splitmix64(state: int, count: int) -> np.ndarray:
 
 
 def gumbel_noise(seed: int, t: int, n: int, R: int) -> np.ndarray:
-    """Noise differences g1 - g0 of step t, [R, n], FP64."""
+    """Noise differences l (= g1 - g0 in law: standard logistic) of step t,
+    [R, n], FP64."""
     out = np.empty((R, n), dtype=np.float64)
     _L().oracle_gumbel_noise(ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), t, n, R, _p(out))
     return out

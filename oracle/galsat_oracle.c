@@ -318,23 +318,21 @@ void oracle_init_state(uint64_t seed, int32_t n, int32_t R, double* x) {
  * The gradient reaching theta1 is G * y1 * (1 - y1) / tau, with G the
  * gradient of loss' at x_hat, and theta0 receives its negative. */
 
-/* Gumbel noise difference for step t: l = g1 - g0 with
- *   g_j = -log(-log(u_j)),  u_j = ((h_j >> 40) + 0.5) * 2^-24,
- *   h_j = mix(seed ^ mix(c_j ^ mix(t + 0x632be59bd9b4e019))),
- *   c_j = v * 2^32 + 2 r + j,
- * mix being the SplitMix64 output mix.  out is [R][n]. */
+/* Gumbel noise difference for step t.  Only l = g1 - g0 of the two
+ * independent Gumbel(0,1) draws enters (Eq. 3-4 with two states), and
+ * that difference is standard logistic, so l is drawn directly by the
+ * logistic quantile function from one uniform:
+ *   l = log(u / (1 - u)),  u = ((h >> 40) + 0.5) * 2^-24,
+ *   h = mix(seed ^ mix(c ^ mix(t + 0x632be59bd9b4e019))),  c = v * 2^32 + r,
+ * mix being the SplitMix64 output mix, evaluated in FP64.  out is [R][n]. */
 void oracle_gumbel_noise(uint64_t seed, int32_t t, int32_t n, int32_t R, double* out) {
   const uint64_t ts = splitmix_mix((uint64_t)(uint32_t)t + 0x632be59bd9b4e019ULL);
   for (int32_t r = 0; r < R; ++r)
     for (int32_t v = 0; v < n; ++v) {
-      double g[2];
-      for (int j = 0; j < 2; ++j) {
-        const uint64_t c = ((uint64_t)(uint32_t)v << 32) + 2 * (uint64_t)(uint32_t)r + (uint64_t)j;
-        const uint64_t h = splitmix_mix(seed ^ splitmix_mix(c ^ ts));
-        const double u = ((double)(h >> 40) + 0.5) * (1.0 / 16777216.0);
-        g[j] = -log(-log(u));
-      }
-      out[(int64_t)r * n + v] = g[1] - g[0];
+      const uint64_t c = ((uint64_t)(uint32_t)v << 32) + (uint64_t)(uint32_t)r;
+      const uint64_t h = splitmix_mix(seed ^ splitmix_mix(c ^ ts));
+      const double u = ((double)(h >> 40) + 0.5) * (1.0 / 16777216.0);
+      out[(int64_t)r * n + v] = log(u / (1.0 - u));
     }
 }
 

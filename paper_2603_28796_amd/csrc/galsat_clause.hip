@@ -21,7 +21,9 @@ __global__ __launch_bounds__(kBlock) void k_clause_pass(ClausePassArgs a) {
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
   const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
-  const int chunk = a.chunk_base + blockIdx.x;
+  const int chunk =
+      a.chunk_order ? ldc(a.chunk_order, a.chunk_base + blockIdx.x) : a.chunk_base + blockIdx.x;
+  if (chunk < 0) return;  // padding of the XCD-aware order: the whole block leaves
   const int tile = a.tile_base + blockIdx.y;
   const int r0 = tile * RT + lane * RPL;
   const bool active = r0 < a.R;
@@ -140,7 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_short_clause(ClausePassArgs a) {
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
   const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
-  const int chunk = a.chunk_base + blockIdx.x;
+  const int chunk =
+      a.chunk_order ? ldc(a.chunk_order, a.chunk_base + blockIdx.x) : a.chunk_base + blockIdx.x;
+  if (chunk < 0) return;  // padding of the XCD-aware order: the whole block leaves
   const int tile = a.tile_base + blockIdx.y;
   const int r0 = tile * RT + lane * RPL;
   const bool active = r0 < a.R;
@@ -237,7 +241,9 @@ __global__ __launch_bounds__(kBlock) void k_wave_clause(ClausePassArgs a) {
   constexpr int WPB = kBlock / 64;
   const int wave = threadIdx.x / 64, lw = threadIdx.x % 64;
   const int grp = lw / LPI, lane = lw % LPI;
-  const int chunk = a.chunk_base + blockIdx.x;
+  const int chunk =
+      a.chunk_order ? ldc(a.chunk_order, a.chunk_base + blockIdx.x) : a.chunk_base + blockIdx.x;
+  if (chunk < 0) return;  // padding of the XCD-aware order: the whole block leaves
   const int tile = a.tile_base + blockIdx.y;
   const int r0 = tile * RT + lane * RPL;
   const bool active = r0 < a.R;

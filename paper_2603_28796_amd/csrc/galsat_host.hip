@@ -29,7 +29,6 @@ thread_local std::string g_create_error;
 
 constexpr int kDefaultRecomputeMaxLen = 8;
 constexpr int kTargetBlocks = 2048;  // blocks per general-pass launch (256 CUs x 8)
-constexpr double kTwoPhaseSkew = 2.0;  // degree skew above which narrow batches go two-phase
 // XCD-contiguous order of one formula: chunk count (about five waves of
 // resident workgroups per XCD) and the id window that counts as local.
 constexpr int64_t kXseqChunks = 6144;
@@ -38,6 +37,7 @@ constexpr int32_t kLocalWindow = 4096;
 constexpr int64_t kCacheBudgetBytes = 256ll << 20;  // state rows one launch may gather from
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 constexpr int64_t kXcdChunks = 160;                 // workgroups resident on one XCD (about)
+constexpr int64_t kXcdChunksTwoPhase = 20;          // measured for the two-phase passes
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -88,12 +88,12 @@ struct Chunks {
 };
 
 Chunks make_chunks(int F, const std::vector<int64_t>& f_item_beg, const std::vector<int64_t>& cost_prefix,
-                   int64_t target) {
+                   int64_t target_all, const std::vector<int64_t>* f_target = nullptr) {
   Chunks c;
   c.f_first.assign((size_t)F + 1, 0);
-  if (target < 1) target = 1;
   for (int f = 0; f < F; ++f) {
     c.f_first[f] = c.count();
+    const int64_t target = std::max<int64_t>(1, f_target ? (*f_target)[f] : target_all);
     int64_t i = f_item_beg[f];
     const int64_t e = f_item_beg[f + 1];
     while (i < e) {
@@ -165,6 +165,8 @@ struct galsat_ctx {
     Chunks ch;
     int32_t *ids = nullptr, *beg = nullptr, *end = nullptr, *row = nullptr;
     int32_t* packed = nullptr;  // short classes: [clauses][2][param] codes, then D rows
+    int32_t* order = nullptr;   // XCD-aware launch order of the chunks (-1: padding)
+    int32_t n_order = 0;
   };
   std::vector<ClauseClass> cls;
   int32_t *segch_beg = nullptr, *segch_end = nullptr, *segch_row = nullptr;
@@ -577,7 +579,6 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
                  &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o);
   const bool csort = csort_o != 0;
-  const int64_t xcd_chunks = xcdc_o >= 0 ? xcdc_o : kXcdChunks;
   int32_t krec;
   if (opt.partials == GALSAT_PARTIALS_STORE) krec = -1;           // every clause stores
   else if (opt.partials == GALSAT_PARTIALS_RECOMPUTE) krec = kmax;
@@ -586,26 +587,20 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   h->ld = (int32_t)round_up(R, 4);
   h->ldD = round_up(R, 4);
   h->stream_items = stream_o >= 0 ? stream_o : 0;
-  // Two-phase gradient (occurrence pass + variable sums): by default for
-  // narrow restart batches (at most 32) on instances whose occurrence counts
-  // are skewed, where the single pass's waves wait on their costliest
-  // variable.  Skew = mean degree seen by an occurrence / mean degree per
-  // variable (about 1 + 1/mean for Poisson degrees).  It needs one
-  // contribution row per occurrence.
-  {
-    double s1 = 0.0, s2 = 0.0;
-    for (int32_t v = 0; v < n; ++v) {
-      const double d = (double)(vp[v + 1] - vp[v]);
-      s1 += d;
-      s2 += d * d;
-    }
-    const double skew = (s1 > 0.0 && n > 0) ? (s2 / s1) / (s1 / n) : 1.0;
-    h->two_phase = two_o >= 0 ? (two_o ? 1 : 0) : ((R <= 32 && skew > kTwoPhaseSkew) ? 1 : 0);
-  }
+  // Two-phase gradient (clause passes + variable sums): by default for
+  // narrow restart batches (at most 32 restarts), where one gather per
+  // literal plus a contribution row written and read beats the single
+  // pass's k - 1 gathers per occurrence; wide batches keep the single pass,
+  // whose gathers are row-wide.  It needs one contribution row per
+  // occurrence.
+  h->two_phase = two_o >= 0 ? (two_o ? 1 : 0) : (R <= 32 ? 1 : 0);
   if (h->two_phase && opt.workspace_budget_bytes > 0 &&
       (size_t)L * (size_t)h->ldD * sizeof(float) > opt.workspace_budget_bytes)
     h->two_phase = 0;
   if (h->stream_items) h->two_phase = 0;
+  // chunks per formula of the XCD-aware order (several formulas per launch)
+  const int64_t xcd_chunks =
+      xcdc_o >= 0 ? xcdc_o : (h->two_phase ? kXcdChunksTwoPhase : kXcdChunks);
   h->tile = choose_tile(R, 4);
   if (h->two_phase && R % 4 == 0 && R >= 16) {
     // four restarts per lane measured faster for the two-phase passes
@@ -781,6 +776,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   const int64_t chunks_target = std::max<int64_t>(1, kTargetBlocks / std::max(1, tiles));
   const int ipb = kBlock / h->tile.lpi;
   std::vector<int32_t> heavy, heavy_sbeg{0}, seg_var, seg_q0, seg_q1, vorder, oorder, vperm;
+  std::vector<int64_t> fcost_all((size_t)F, 0);  // gather cost of each formula
   std::vector<int32_t> heavy_f_first((size_t)F + 1, 0);
   {
     std::vector<int64_t> vcost((size_t)n, 1);
@@ -817,7 +813,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     vc.f_first.assign((size_t)F + 1, 0);
     sc.f_first.assign((size_t)F + 1, 0);
     const bool per_formula = opt.schedule == GALSAT_SCHED_PLAIN;
-    std::vector<int64_t> fcost((size_t)F, 0);
+    std::vector<int64_t>& fcost = fcost_all;
     for (int32_t f = 0; f < F; ++f) {
       vc.f_first[f] = vc.count();
       heavy_f_first[f] = (int32_t)heavy.size();
@@ -972,12 +968,48 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       if (xcd) xcd_order(oc, &oorder);
     }
   }
+  // One formula per launch (PLAIN): size each formula's clause chunks as if
+  // it were the whole problem, as for its variable chunks, so each launch
+  // still spreads over the chip.
+  std::vector<int64_t> plain_targets;
+  auto per_formula_targets = [&](const std::vector<int64_t>& fb,
+                                 const std::vector<int64_t>& pre) -> const std::vector<int64_t>* {
+    if (opt.schedule != GALSAT_SCHED_PLAIN) return nullptr;
+    plain_targets.assign((size_t)F, 64);
+    for (int32_t f = 0; f < F; ++f)
+      plain_targets[f] = std::max<int64_t>(64, (pre[fb[f + 1]] - pre[fb[f]]) / chunks_target);
+    return &plain_targets;
+  };
   {
     std::vector<int64_t> pre(stored_ids.size() + 1, 0);
     for (size_t i = 0; i < stored_ids.size(); ++i)
       pre[i + 1] = pre[i] + 1 + 2 * (cp[stored_ids[i] + 1] - cp[stored_ids[i]]);
-    h->sch = make_chunks(F, f_sbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target));
+    h->sch = make_chunks(F, f_sbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target),
+                         per_formula_targets(f_sbeg, pre));
   }
+  // XCD-aware order of the clause classes' chunks (several formulas per
+  // launch): the same formula groups as the variable chunks, so a formula's
+  // clause and variable work run on the same XCD.
+  const bool xcd_all = F > 1 && opt.schedule != GALSAT_SCHED_PLAIN && xcd_chunks > 0;
+  auto xcd_order_all = [&](const Chunks& ch, std::vector<int32_t>* order) {
+    std::vector<int32_t> ford(F);
+    for (int32_t f = 0; f < F; ++f) ford[f] = f;
+    std::stable_sort(ford.begin(), ford.end(),
+                     [&](int32_t a2, int32_t b2) { return fcost_all[a2] > fcost_all[b2]; });
+    std::vector<int64_t> load(kXcds, 0);
+    std::vector<std::vector<int32_t>> lists(kXcds);
+    for (int32_t f : ford) {
+      const int gsel = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[gsel] += fcost_all[f];
+      for (int32_t cid = ch.f_first[f]; cid < ch.f_first[f + 1]; ++cid) lists[gsel].push_back(cid);
+    }
+    size_t longest = 0;
+    for (auto& l : lists) longest = std::max(longest, l.size());
+    order->assign(longest * kXcds, -1);
+    for (int gsel = 0; gsel < kXcds; ++gsel)
+      for (size_t i = 0; i < lists[gsel].size(); ++i) (*order)[i * kXcds + gsel] = lists[gsel][i];
+  };
+  std::vector<std::vector<int32_t>> cls_order((size_t)NCL);
   h->cls.resize((size_t)NCL);
   for (int c = 0; c < NCL; ++c) {
     const std::vector<int32_t>& ids = cls_ids[c];
@@ -985,7 +1017,18 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     for (size_t i = 0; i < ids.size(); ++i) pre[i + 1] = pre[i] + 1 + (cp[ids[i] + 1] - cp[ids[i]]);
     h->cls[c].kind = routes[c].kind;
     h->cls[c].param = routes[c].param;
-    h->cls[c].ch = make_chunks(F, cls_fbeg[c], pre, std::max<int64_t>(64, pre.back() / chunks_target));
+    if (xcd_all) {
+      // several formulas per launch: about xcd_chunks chunks per formula,
+      // in the formula groups of the variable chunks' XCD order
+      std::vector<int64_t> ft((size_t)F);
+      for (int32_t f = 0; f < F; ++f)
+        ft[f] = std::max<int64_t>(64, (pre[cls_fbeg[c][f + 1]] - pre[cls_fbeg[c][f]]) / xcd_chunks);
+      h->cls[c].ch = make_chunks(F, cls_fbeg[c], pre, 0, &ft);
+      xcd_order_all(h->cls[c].ch, &cls_order[c]);
+    } else {
+      h->cls[c].ch = make_chunks(F, cls_fbeg[c], pre, std::max<int64_t>(64, pre.back() / chunks_target),
+                                 per_formula_targets(cls_fbeg[c], pre));
+    }
   }
   {
     std::vector<int64_t> pre((size_t)m + 1, 0), fb(fcb.begin(), fcb.end());
@@ -1118,6 +1161,11 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   }
   for (int k = 0; k < NCL; ++k) {
     galsat_ctx::ClauseClass& cc = c->cls[k];
+    cc.n_order = (int32_t)cls_order[k].size();
+    if (cc.n_order > 0 &&
+        (he = c->upload(&cc.order, cls_order[k].data(), cls_order[k].size(), s)) != hipSuccess)
+      return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
+                         std::string("upload clause order: ") + hipGetErrorString(he));
     if (!cls_packed[k].empty() &&
         (he = c->upload(&cc.packed, cls_packed[k].data(), cls_packed[k].size(), s)) != hipSuccess)
       return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
@@ -1386,6 +1434,12 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
       ca.chunk_cend = cc.end;
       ca.chunk_row = cc.row;
       ca.chunk_base = c0;
+      int blocks = c1 - c0;
+      if (cc.n_order > 0 && f0 == 0 && f1 == h->F) {
+        ca.chunk_order = cc.order;
+        ca.chunk_base = 0;
+        blocks = cc.n_order;
+      }
       ca.tile_base = tb;
       ca.tile_count = tc;
       ca.x = x;
@@ -1397,13 +1451,13 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
       ca.R = h->R;
       ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
       if (cc.kind == kClassShort) {
-        GS_HIP(h, launch_short_clause(ca, t, cc.param, c1 - c0, s), "short clause pass");
+        GS_HIP(h, launch_short_clause(ca, t, cc.param, blocks, s), "short clause pass");
       } else if (t.lpi == h->tile.lpi && t.rpl == h->tile.rpl) {
-        GS_HIP(h, launch_wave_clause(ca, t, cc.param, c1 - c0, s), "wave clause pass");
+        GS_HIP(h, launch_wave_clause(ca, t, cc.param, blocks, s), "wave clause pass");
       } else {
         // the classes were routed for the planned tile; a fallback tile
         // (unaligned caller buffers) runs them through the sweeping pass
-        GS_HIP(h, launch_clause_pass(ca, true, t, c1 - c0, s), "clause pass");
+        GS_HIP(h, launch_clause_pass(ca, true, t, blocks, s), "clause pass");
       }
     }
     va.tile_base = tb;

@@ -79,6 +79,7 @@ struct ClausePassArgs {
   const int32_t* chunk_cbeg;    // [chunks] range in the clause list
   const int32_t* chunk_cend;
   const int32_t* chunk_row;     // [chunks] partial-sum row, or null for row = chunk
+  const int32_t* chunk_order;   // block -> chunk (-1: the block does nothing), or null
   int32_t chunk_base;
   int32_t tile_base;            // first restart tile of this launch
   int32_t tile_count;           // restart tiles of this launch (0: all from tile_base)

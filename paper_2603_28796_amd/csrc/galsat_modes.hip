@@ -12,20 +12,17 @@ namespace galsat {
 // logit difference d = theta1 - theta0 and the noise difference
 // l = g1 - g0 matter: y1 = sigma((d + l) / tau), x_hat = [d + l > 0].
 
-// Noise difference of step t for (v, r): g_j = -log(-log(u_j)) with
-// u_j = ((h_j >> 40) + 0.5) * 2^-24 and h_j the SplitMix64 mix of
-// (seed, v * 2^32 + 2r + j, t), evaluated in FP64 and rounded once.
+// Noise difference of step t for (v, r).  The difference of two
+// independent Gumbel(0,1) draws is standard logistic, so it is drawn
+// directly by the logistic quantile function from one uniform:
+// l = log(u / (1 - u)), u = ((h >> 40) + 0.5) * 2^-24, h the SplitMix64 mix
+// of (seed, v * 2^32 + r, t); evaluated in FP64 and rounded once.
 __device__ __forceinline__ float gumbel_diff(uint64_t seed, int t, int64_t v, int r) {
   const uint64_t ts = splitmix_mix((uint64_t)(uint32_t)t + 0x632be59bd9b4e019ULL);
-  double g[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const uint64_t c = ((uint64_t)(uint32_t)v << 32) + 2 * (uint64_t)(uint32_t)r + (uint64_t)j;
-    const uint64_t h = splitmix_mix(seed ^ splitmix_mix(c ^ ts));
-    const double u = ((double)(h >> 40) + 0.5) * (1.0 / 16777216.0);
-    g[j] = -log(-log(u));
-  }
-  return (float)(g[1] - g[0]);
+  const uint64_t c = ((uint64_t)(uint32_t)v << 32) + (uint64_t)(uint32_t)r;
+  const uint64_t h = splitmix_mix(seed ^ splitmix_mix(c ^ ts));
+  const double u = ((double)(h >> 40) + 0.5) * (1.0 / 16777216.0);
+  return (float)log(u / (1.0 - u));
 }
 
 __global__ __launch_bounds__(256) void k_gumbel_noise(float* out, int32_t ldo, int32_t n, int32_t R,

@@ -122,7 +122,7 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
   if (base.partials == GALSAT_PARTIALS_AUTO && kmax > 8 && long_lits > 0)
     krecs = {",krec=8", ",krec=" + std::to_string(kmax)};
   std::vector<std::string> xcd = {""};
-  if (prob->num_formulas > 1 && base.schedule != GALSAT_SCHED_PLAIN) xcd = {",xcdc=160", ",xcdc=40"};
+  if (prob->num_formulas > 1 && base.schedule != GALSAT_SCHED_PLAIN) xcd = {"", ",xcdc=160", ",xcdc=20"};
   // narrow restart batches: the single pass against the two-phase gradient
   std::vector<std::string> twos = {""};
   if (R <= 64) twos = {",two=0", ",two=1"};
