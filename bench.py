@@ -82,6 +82,37 @@ def algorithmic_bytes(cnf, R, info, optimizer):
     return b
 
 
+def stream_copy_gbps(nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """Device-to-device copy bandwidth on this GPU (bytes read + written per
+    second), the measured counterpart of the HBM peak."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    return gbps
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cnf, R, lr, budget_s: float):
     """The FP64 oracle's full step (gradient, unsat count, update) on the same
     instance, all restarts, repeated until about budget_s seconds."""
@@ -98,6 +129,7 @@ def cpu_baseline(cnf, R, lr, budget_s: float):
         steps += 1
     v = R * cnf.L * steps / t
     return {"value": v, "unit": "literal-evals/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"{steps} full FP64 steps (all {R} restarts) of the same instance, "
                       f"{t:.1f} s", "seconds": round(t, 2)}
 
@@ -301,11 +333,15 @@ def main():
             ab = algorithmic_bytes(cnf, R, info, "sgd") / per_step
             achieved = ab / (avg_ms / 1e3) / 1e9
             traffic = read_traffic(w.key, "var_pass")
+            copy = stream_copy_gbps()
             roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "traffic": traffic, "kernel": "k_var_pass",
                         "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_ms, 5),
-                        "launches_per_step": per_step}
+                        "launches_per_step": per_step,
+                        # measured traffic rate and a measured copy on the same GPU
+                        "traffic_GBps": round(traffic / (avg_ms / 1e3) / 1e9, 1) if traffic else None,
+                        "stream_copy_GBps": round(copy, 1)}
 
     gumbel = None
     if args.gumbel_steps > 0 and not args.tseitin:
