@@ -104,13 +104,17 @@ enum { GALSAT_OPT_SGD_CLAMP = 0, GALSAT_OPT_ADAM = 1 };
 
 /* How the backward obtains each literal's partial derivative
  * prod_{i != j} (1 - s_i):
- *   STORE      a clause-parallel pass forms them from prefix and suffix
- *              products and stores them; a variable-parallel pass sums
+ *   STORE      clause-parallel passes form them from prefix and suffix
+ *              products and store them; a variable-parallel pass sums
  *              them in var_occ order.
- *   RECOMPUTE  the variable-parallel pass recomputes them from x, so no
+ *   RECOMPUTE  the variable-parallel side recomputes them from x, so no
  *              per-literal or per-clause values are kept between passes.
- *   AUTO       clauses up to recompute_max_len literals recompute, longer
- *              ones store, within workspace_budget_bytes. */
+ *   AUTO       the plan's choice, within workspace_budget_bytes: with the
+ *              single-pass gradient (more than 32 restarts), clauses up to
+ *              recompute_max_len literals (default 8) recompute and longer
+ *              ones store; with the two-phase gradient (at most 32
+ *              restarts), every clause stores, unless recompute_max_len is
+ *              set. */
 enum { GALSAT_PARTIALS_AUTO = 0, GALSAT_PARTIALS_STORE = 1, GALSAT_PARTIALS_RECOMPUTE = 2 };
 
 /* Execution schedule of galsat_step:
