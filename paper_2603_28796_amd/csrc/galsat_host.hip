@@ -29,9 +29,10 @@ thread_local std::string g_create_error;
 
 constexpr int kDefaultRecomputeMaxLen = 8;
 constexpr int kTargetBlocks = 2048;  // blocks per general-pass launch (256 CUs x 8)
-// XCD-contiguous order of one formula: chunk count (about five waves of
-// resident workgroups per XCD) and the id window that counts as local.
-constexpr int64_t kXseqChunks = 6144;
+// XCD-contiguous order of one formula: chunk count (measured; 2,048 per
+// XCD) and the id window that counts as local.
+constexpr int64_t kXseqChunks = 16384;
+constexpr int kSegDivSinglePass = 16;  // single-pass segment = one item's share / 16 (measured)
 constexpr int kClassShort = 0, kClassWave = 1;  // passes of the stored-clause classes
 constexpr int32_t kLocalWindow = 4096;
 constexpr int64_t kCacheBudgetBytes = 256ll << 20;  // state rows one launch may gather from
@@ -370,7 +371,7 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // (one formula: about this many chunks in an XCD-contiguous order).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
                     int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
-                    int* short_clauses, int* xseq) {
+                    int* short_clauses, int* xseq, int* segdiv) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -394,6 +395,7 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "wave") *wave = v;
       else if (k == "short") *short_clauses = v;
       else if (k == "xseq") *xseq = v;
+      else if (k == "segdiv") *segdiv = v;
     }
     pos = comma + 1;
   }
@@ -575,9 +577,9 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
 
   // ---- plan: which clauses recompute their partials in the variable pass
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
-  int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1;
+  int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1, segdiv_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
-                 &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o);
+                 &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o);
   const bool csort = csort_o != 0;
   int32_t krec;
   if (opt.partials == GALSAT_PARTIALS_STORE) krec = -1;           // every clause stores
@@ -788,6 +790,11 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     for (int32_t v = 0; v < n; ++v) total += vcost[v];
     int64_t target = std::max<int64_t>(64, total / chunks_target);
     const int64_t item_cap = std::max<int64_t>(64, target / ipb);
+    // segments of a split variable: in the single pass a fraction of one
+    // item's share, so the hottest variables' gathers spread over many
+    // waves; the two-phase plan's segments only read contribution rows
+    const int segdiv = segdiv_o > 0 ? segdiv_o : (two ? 1 : kSegDivSinglePass);
+    const int64_t seg_cap = std::max<int64_t>(64, item_cap / segdiv);
     // XCD-contiguous order (one formula): many small chunks, each XCD taking
     // a contiguous run of them, so the workgroups resident on an XCD cover a
     // narrow range of variable ids and share the rows they gather in its L2
@@ -846,7 +853,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
           int32_t q0 = vp[v];
           for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
             sacc += occ_cost[q];
-            if (sacc >= item_cap_f || q + 1 == vp[v + 1]) {
+            if (sacc >= seg_cap || q + 1 == vp[v + 1]) {
               seg_var.push_back(v);
               seg_q0.push_back(q0);
               seg_q1.push_back(q + 1);
