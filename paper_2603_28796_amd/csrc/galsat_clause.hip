@@ -367,21 +367,48 @@ __global__ __launch_bounds__(kBlock) void k_wave_clause(ClausePassArgs a) {
 //
 // loss[f][r] = sum of the formula's partial rows (fixed order) + empty
 // clauses; the same for the unsat count.
-// W waves per block: wave w sums rows w, w + W, ... for 64 restarts, then
-// the W partial sums are combined pairwise in a fixed tree.
+// W waves per block: wave w sums rows w, w + W, ... for 64 restarts into
+// eight interleaved accumulators (eight rows in flight), which are added in
+// a fixed order; then the W partial sums are combined pairwise in a fixed
+// tree.
+// With a.split > 1, block x handles part x % split of formula x / split and
+// writes its sums (without the empty clauses) to part_l / part_u.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_finalize(FinalizeArgs a) {
-  const int f = a.f_base + blockIdx.x;
+  constexpr int U = 8;
+  const int fl = blockIdx.x / a.split, part = blockIdx.x % a.split;
+  const int f = a.f_base + fl;
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int r = blockIdx.y * 64 + lane;
   const int R = a.R;
   double acc = 0.0;
   int uacc = 0;
   if (r < R) {
-    const int rb = a.a_beg[f], re = a.a_end[f];
-    for (int row = rb + w; row < re; row += W) {
-      if (a.loss_out) acc += a.loss_part[(int64_t)row * R + r];
-      if (a.unsat_out) uacc += a.unsat_part[(int64_t)row * R + r];
+    const int fb = a.a_beg[f], fe = a.a_end[f];
+    const int rb = fb + (int)((int64_t)(fe - fb) * part / a.split);
+    const int re = fb + (int)((int64_t)(fe - fb) * (part + 1) / a.split);
+    double al[U];
+    int au[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) { al[u] = 0.0; au[u] = 0; }
+    int row = rb + w;
+    for (; row + (U - 1) * W < re; row += U * W) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = (int64_t)(row + u * W) * R + r;
+        if (a.loss_out) al[u] += a.loss_part[i];
+        if (a.unsat_out) au[u] += a.unsat_part[i];
+      }
+    }
+    for (int u = 0; row < re; row += W, ++u) {
+      const int64_t i = (int64_t)row * R + r;
+      if (a.loss_out) al[u] += a.loss_part[i];
+      if (a.unsat_out) au[u] += a.unsat_part[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc += al[u];
+      uacc += au[u];
     }
   }
   __shared__ double sl[64 * W];
@@ -398,11 +425,32 @@ __global__ __launch_bounds__(64 * W) void k_finalize(FinalizeArgs a) {
     __syncthreads();
   }
   if (w == 0 && r < R) {
-    const double tot = sl[lane] + (double)a.n_empty[f];
-    const int utot = su[lane] + a.n_empty[f];
-    if (a.loss_out) a.loss_out[(int64_t)f * R + r] = (float)tot;
-    if (a.unsat_out) a.unsat_out[(int64_t)f * R + r] = utot;
+    if (a.split > 1) {
+      a.part_l[(int64_t)blockIdx.x * R + r] = sl[lane];
+      a.part_u[(int64_t)blockIdx.x * R + r] = su[lane];
+    } else {
+      const double tot = sl[lane] + (double)a.n_empty[f];
+      const int utot = su[lane] + a.n_empty[f];
+      if (a.loss_out) a.loss_out[(int64_t)f * R + r] = (float)tot;
+      if (a.unsat_out) a.unsat_out[(int64_t)f * R + r] = utot;
+    }
   }
+}
+
+// Second stage of the split finalize: the parts of each formula in order.
+__global__ __launch_bounds__(64) void k_finalize_parts(FinalizeArgs a) {
+  const int fl = blockIdx.x, f = a.f_base + fl;
+  const int r = blockIdx.y * 64 + threadIdx.x;
+  const int R = a.R;
+  if (r >= R) return;
+  double tot = 0.0;
+  int utot = 0;
+  for (int p = 0; p < a.split; ++p) {
+    tot += a.part_l[((int64_t)fl * a.split + p) * R + r];
+    utot += a.part_u[((int64_t)fl * a.split + p) * R + r];
+  }
+  if (a.loss_out) a.loss_out[(int64_t)f * R + r] = (float)(tot + (double)a.n_empty[f]);
+  if (a.unsat_out) a.unsat_out[(int64_t)f * R + r] = utot + a.n_empty[f];
 }
 
 // ---------------------------------------------------------- init / copy
@@ -618,14 +666,32 @@ hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int
   }
 }
 
-hipError_t launch_finalize(const FinalizeArgs& a, int F, hipStream_t s) {
+hipError_t launch_finalize(const FinalizeArgs& a_in, int F, hipStream_t s) {
   if (F <= 0) return hipSuccess;
-  dim3 grid(F, (a.R + 63) / 64);
-  // few large formulas: more waves per formula; many small ones: fewer
-  if ((int64_t)F * grid.y < 256)
-    hipLaunchKernelGGL((k_finalize<16>), grid, dim3(1024), 0, s, a);
-  else
+  FinalizeArgs a = a_in;
+  const int gy = (a.R + 63) / 64;
+  // few formulas x restart groups: cut each formula's rows into parts
+  // summed by separate workgroups (about 512 workgroups in all), when the
+  // part sums fit the workspace
+  a.split = 1;
+  if ((int64_t)F * gy < 512 && a.part_l && a.part_u) {
+    const int64_t want = (512 + (int64_t)F * gy - 1) / ((int64_t)F * gy);
+    const int64_t fit = kFinalizeScratch / ((int64_t)F * a.R);
+    const int64_t rows = std::max<int64_t>(1, a.max_rows / 256);  // >= 256 rows a part
+    a.split = (int)std::max<int64_t>(1, std::min(std::min(want, fit), rows));
+  }
+  dim3 grid(F * a.split, gy);
+  if (a.split > 1) {
     hipLaunchKernelGGL((k_finalize<4>), grid, dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize_parts, dim3(F, gy), dim3(64), 0, s, a);
+  } else if ((int64_t)F * gy < 256) {
+    // few large formulas: more waves per formula; many small ones: fewer
+    hipLaunchKernelGGL((k_finalize<16>), grid, dim3(1024), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_finalize<4>), grid, dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -186,6 +186,9 @@ struct galsat_ctx {
   float* nbuf = nullptr;  // noise of the straight-through Gumbel mode (allocated on first use)
   int32_t* sel_off = nullptr;  // per-formula selection offsets of galsat_select_vars
   double* loss_part = nullptr;
+  double* fin_l = nullptr;     // split-finalize part sums (kFinalizeScratch entries)
+  int32_t* fin_u = nullptr;
+  int32_t max_step_rows = 0, max_all_rows = 0;  // most partial rows of one formula
   double* gseg = nullptr;
   int32_t* unsat_part = nullptr;
   uint64_t* bits = nullptr;
@@ -1194,6 +1197,10 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(seg_q1, seg_q1);
   UP(heavy_var, heavy);
   UP(heavy_sbeg, heavy_sbeg);
+  for (int32_t f = 0; f < F; ++f) {
+    c->max_step_rows = std::max(c->max_step_rows, frow1[f] - frow0[f]);
+    c->max_all_rows = std::max(c->max_all_rows, faa1[f] - faa0[f]);
+  }
   UP(fin_step_a0, frow0);
   UP(fin_step_a1, frow1);
   UP(fin_all_a0, faa0);
@@ -1212,6 +1219,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   AL(unsat_part, (size_t)std::max<int64_t>(rows, 1) * R);
   AL(bits, (size_t)n * ((R + 63) / 64));
   AL(best_tmp, F);
+  AL(fin_l, kFinalizeScratch);
+  AL(fin_u, kFinalizeScratch);
   AL(unsat_tmp, (size_t)F * R);
   AL(work_counter, 1);
 #undef UP
@@ -1512,7 +1521,7 @@ galsat_status finalize_step(galsat_ctx* h, float* loss, int32_t* unsat, int f0, 
                             hipStream_t s) {
   if (!loss && !unsat) return GALSAT_OK;
   FinalizeArgs fa{h->fin_step_a0, h->fin_step_a1, h->n_empty, h->loss_part, h->unsat_part,
-                  loss, unsat, h->R, f0};
+                  loss, unsat, h->R, f0, h->fin_l, h->fin_u, 1, h->max_step_rows};
   ProfScope _ps(h, GALSAT_K_FINALIZE, s);
   GS_HIP(h, launch_finalize(fa, f1 - f0, s), "finalize");
   return GALSAT_OK;
@@ -1548,7 +1557,7 @@ extern "C" galsat_status galsat_loss_grad(galsat_handle h, const float* x, int32
       GS_HIP(h, launch_clause_pass(a, false, t, h->ach.count(), s), "clause pass");
     }
     FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->zero_empty, h->loss_part, h->unsat_part,
-                    loss, nullptr, h->R, 0};
+                    loss, nullptr, h->R, 0, h->fin_l, h->fin_u, 1, h->max_all_rows};
     ProfScope _ps(h, GALSAT_K_FINALIZE, s);
     GS_HIP(h, launch_finalize(fa, F, s), "finalize");
     return GALSAT_OK;
@@ -1841,7 +1850,7 @@ extern "C" galsat_status galsat_round_check(galsat_handle h, const float* x, int
            "count unsat");
   }
   FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->zero_empty, h->loss_part, h->unsat_part,
-                  nullptr, unsat, h->R, 0};
+                  nullptr, unsat, h->R, 0, h->fin_l, h->fin_u, 1, h->max_all_rows};
   {
     ProfScope _ps(h, GALSAT_K_FINALIZE, s);
     GS_HIP(h, launch_finalize(fa, h->F, s), "finalize");

@@ -102,7 +102,17 @@ struct FinalizeArgs {
   int32_t* unsat_out;           // [F*R] or null
   int32_t R;
   int32_t f_base;
+  // split > 1: each formula's rows are cut into `split` contiguous parts
+  // summed by separate workgroups into part_l / part_u ([F*split][R]), then
+  // added in part order by a second kernel (launch_finalize sets these)
+  double* part_l;
+  int32_t* part_u;
+  int32_t split;
+  int32_t max_rows;             // most partial rows of one formula (host value; caps split)
 };
+
+// Workspace of the split finalize: entries of part_l and part_u.
+constexpr int64_t kFinalizeScratch = 1024 * 64;
 
 enum VarMode { kModeSGD = 0, kModeAdam = 1, kModeGrad = 2 };
 
