@@ -178,3 +178,23 @@ def test_planning_completes_for_every_plan(plan, partials):
             lib.galsat_destroy(h)
         else:
             assert st == -3, (R, lib.galsat_last_error(None))
+
+
+def test_rejects_restarts_beyond_index_range(small):
+    st, msg, h = _create(small, R=65537)
+    assert st == -4 and not h.value
+
+
+@pytest.mark.parametrize("clauses,n", [([], 3), ([[]], 2), ([], 0), ([[1]], 1), ([[], []], 1),
+                                       ([[1, -1], [2, 2, 2]], 2)])
+def test_planning_degenerate_formulas(clauses, n):
+    """No clauses, only empty clauses, no variables, a tautology and a
+    repeated literal: planning completes (up to the first upload without a
+    GPU)."""
+    cnf = I.from_clauses(clauses, n=n)
+    for R in (1, 16, 100):
+        st, msg, h = _create(cnf, R=R)
+        if st == 0:
+            G.load_library().galsat_destroy(h)
+        else:
+            assert st == -3, (R, msg)

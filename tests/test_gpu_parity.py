@@ -275,6 +275,27 @@ def test_two_phase_adam_and_upstream():
     assert torch.equal(sa, sb)
 
 
+@pytest.mark.parametrize("clauses,n", [([], 3), ([[]], 2), ([], 0), ([[1]], 1), ([[], []], 1),
+                                       ([[1, -1], [2, 2, 2]], 2)])
+@pytest.mark.parametrize("R", [1, 16, 100])
+def test_degenerate_formulas(clauses, n, R):
+    """No clauses, only empty clauses, no variables, a tautology and a
+    repeated literal, through both gradient plans."""
+    say(f"[degenerate] {clauses} n={n} R={R}")
+    cnf = I.from_clauses(clauses, n=n)
+    for plan in ("two=0", "two=1"):
+        prob = Problem(cnf, R, plan_override=plan)
+        x = _x0(cnf.n, R, 81)
+        parity_at(prob, cnf, x, f"degenerate {plan}")
+        xr = to_oracle(x, R)
+        _, g_ref, _ = oracle.grad(cnf, xr, with_abs=True)
+        x1 = x.clone()
+        lt, ut = prob.step(x1, 1, trace=True)
+        torch.cuda.synchronize()
+        check_counts(ut[0], oracle.unsat(cnf, xr), "degenerate step trace")
+        check_update(x1, oracle.step_sgd(xr, g_ref, prob.lr), xr, R, "degenerate step")
+
+
 def test_unaligned_and_padded_state():
     say("[layout] padded and odd row strides")
     cnf = CASES["planted300"]()
