@@ -120,11 +120,22 @@ enum { GALSAT_PARTIALS_AUTO = 0, GALSAT_PARTIALS_STORE = 1, GALSAT_PARTIALS_RECO
 /* Execution schedule of galsat_step:
  *   GENERAL  multi-kernel passes per step over all formulas at once (the
  *            formulas' work items share every launch);
+ *   LDS      one persistent launch runs every step: one workgroup per
+ *            (formula, restart group) with that group's state double-
+ *            buffered in LDS, and the formula's occurrence records too when
+ *            they fit.  For small formulas (12 bytes per variable of the
+ *            largest formula within 64 KB of LDS: up to about 5,400
+ *            variables); projected SGD only, every clause recomputed.
+ *            galsat_create returns GALSAT_EUNSUPPORTED otherwise.  States and
+ *            unsat counts equal GENERAL's with every clause recomputed and
+ *            the single-pass gradient bitwise (no variable split); the loss
+ *            trace is summed in another fixed order.  The other entry points
+ *            run the general passes;
  *   PLAIN    one formula at a time, kernels launched per pass per step
  *            (the reference point for batching, not a fast path);
- *   AUTO     GENERAL.
- * The value 2 is not used; galsat_create rejects it. */
-enum { GALSAT_SCHED_AUTO = 0, GALSAT_SCHED_GENERAL = 1, GALSAT_SCHED_PLAIN = 3 };
+ *   AUTO     GENERAL. */
+enum { GALSAT_SCHED_AUTO = 0, GALSAT_SCHED_GENERAL = 1, GALSAT_SCHED_LDS = 2,
+       GALSAT_SCHED_PLAIN = 3 };
 
 typedef struct {
   int32_t optimizer;         /* GALSAT_OPT_*; default SGD_CLAMP */
@@ -145,7 +156,11 @@ typedef struct {
                               variable items / length-sorted stored clauses, 0 or 1),
                               wave / short (0: no wave-per-clause / short-clause pass),
                               xseq (one formula: chunks of the XCD-contiguous order,
-                              0: off).  Keys left out take the plan's own choice. */
+                              0: off), segdiv (heavy-variable split divisor), ldsrg
+                              (LDS schedule: restarts per workgroup, 1, 2, 4, 8, 16 or
+                              32), ldsstage (0: the LDS schedule reads the records from
+                              global memory).  Keys left out take the plan's own
+                              choice. */
 } galsat_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -197,7 +212,8 @@ galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, float* opt_sta
  * of galsat_step with exactly these arguments without running it, so the
  * next galsat_step call with the same arguments only replays it.  Returns
  * GALSAT_EUNSUPPORTED when the call would run eagerly (no use_graph, Adam,
- * or profiling enabled). */
+ * or profiling enabled); with the LDS schedule (a single launch already)
+ * it does nothing. */
 galsat_status galsat_step_prepare(galsat_handle h, float* x, int32_t ldx, float* opt_state,
                                   int32_t steps, float* loss_trace, int32_t* unsat_trace);
 

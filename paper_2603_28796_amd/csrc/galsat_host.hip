@@ -31,6 +31,9 @@ constexpr int kDefaultRecomputeMaxLen = 8;
 constexpr int kTargetBlocks = 2048;  // blocks per general-pass launch (256 CUs x 8)
 // XCD-contiguous order of one formula: chunk count (measured; 2,048 per
 // XCD) and the id window that counts as local.
+// Workgroups of the LDS schedule up to which every restart gets its own
+// (two per CU of the 256).
+constexpr int64_t kPersistSpreadGroups = 512;
 constexpr int64_t kXseqChunks = 16384;
 constexpr int kSegDivSinglePass = 16;  // single-pass segment = one item's share / 16 (measured)
 constexpr int kClassShort = 0, kClassWave = 1;  // passes of the stored-clause classes
@@ -133,6 +136,10 @@ struct galsat_ctx {
   int stream_items = 0;  // streaming variable pass
   int two_phase = 0;     // occurrence pass + variable sum instead of the single pass
   int32_t xseq = 0;      // chunks of the XCD-contiguous order (0: off)
+  int lds_rg = 0;        // restart group of the persistent LDS schedule (0: not used)
+  int lds_stage = 0;     // its occurrence records staged in LDS
+  int32_t lds_nocc = 0;  // most occurrences of one formula
+  int32_t nf_max = 0;    // most variables of one formula
   int32_t ld = 0;    // internal state row stride (floats)
   int64_t ldD = 0;
   int adam_t = 0;
@@ -371,10 +378,12 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // stream (1: streaming variable pass), two (1: two-phase gradient), dsort
 // (1: cost-sorted variable items), csort (1: length-sorted stored clauses),
 // wave (0: no wave-per-clause pass), short (0: no short-clause pass), xseq
-// (one formula: about this many chunks in an XCD-contiguous order).
+// (one formula: about this many chunks in an XCD-contiguous order), segdiv,
+// ldsrg (restarts per workgroup of the LDS schedule: 1, 2, 4, 8, 16 or 32)
+// and ldsstage (0: the LDS schedule reads records from global memory).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
                     int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
-                    int* short_clauses, int* xseq, int* segdiv) {
+                    int* short_clauses, int* xseq, int* segdiv, int* ldsrg, int* ldsstage) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -399,6 +408,8 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "short") *short_clauses = v;
       else if (k == "xseq") *xseq = v;
       else if (k == "segdiv") *segdiv = v;
+      else if (k == "ldsrg") *ldsrg = v;
+      else if (k == "ldsstage") *ldsstage = v;
     }
     pos = comma + 1;
   }
@@ -445,7 +456,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     return create_fail(GALSAT_EINVAL, "unknown optimizer");
   if (opt.partials < 0 || opt.partials > 2) return create_fail(GALSAT_EINVAL, "unknown partials mode");
   if (opt.schedule != GALSAT_SCHED_AUTO && opt.schedule != GALSAT_SCHED_GENERAL &&
-      opt.schedule != GALSAT_SCHED_PLAIN)
+      opt.schedule != GALSAT_SCHED_LDS && opt.schedule != GALSAT_SCHED_PLAIN)
     return create_fail(GALSAT_EINVAL, "unknown schedule");
   if (!(opt.lr >= 0.0f) || !std::isfinite(opt.lr)) return create_fail(GALSAT_EINVAL, "lr must be finite and >= 0");
 
@@ -581,14 +592,56 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // ---- plan: which clauses recompute their partials in the variable pass
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
   int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1, segdiv_o = -1;
+  int ldsrg_o = 0, ldsstage_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
-                 &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o);
+                 &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o, &ldsrg_o, &ldsstage_o);
   const bool csort = csort_o != 0;
+  // Persistent LDS schedule: every formula's restart group must fit in LDS
+  // (state double-buffered); SGD only; every clause recomputed.
+  int lds_rg = 0, lds_stage = 0;
+  int32_t lds_nocc = 0;
+  if (opt.schedule == GALSAT_SCHED_LDS) {
+    if (opt.optimizer != GALSAT_OPT_SGD_CLAMP || opt.partials == GALSAT_PARTIALS_STORE)
+      return create_fail(GALSAT_EUNSUPPORTED, "the LDS schedule runs projected SGD with recomputed partials");
+    int32_t nf_max = 0;
+    for (int32_t f = 0; f < F; ++f) {
+      nf_max = std::max(nf_max, fvb[f + 1] - fvb[f]);
+      lds_nocc = std::max(lds_nocc, vp[fvb[f + 1]] - vp[fvb[f]]);
+    }
+    int dev = 0, lds_max = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        lds_max <= 0)
+      lds_max = 64 << 10;
+    lds_max = std::min(lds_max, 64 << 10);
+    // Restarts per workgroup: one (a workgroup per restart, the most
+    // parallel) while that gives at most two workgroups per CU; beyond, up
+    // to 32 and no more than the restarts, as long as every variable of the
+    // largest formula keeps its own slot of the 512 threads (a step makes
+    // one pass over the variables).  Fewer when the state does not fit.
+    // The records are staged when they fit beside it.
+    int rg = 1;
+    while (rg < 32 && rg < R && (int64_t)(kPersistBlock / (2 * rg)) >= nf_max &&
+           (int64_t)F * ((R + rg - 1) / rg) > kPersistSpreadGroups)
+      rg *= 2;
+    if (ldsrg_o == 1 || ldsrg_o == 2 || ldsrg_o == 4 || ldsrg_o == 8 || ldsrg_o == 16 || ldsrg_o == 32)
+      rg = ldsrg_o;
+    for (; rg >= 1 && !lds_rg; rg /= 2) {
+      if (ldsstage_o != 0 && persist_lds_bytes(rg, nf_max, lds_nocc) <= (size_t)lds_max) {
+        lds_rg = rg;
+        lds_stage = 1;
+      } else if (persist_lds_bytes(rg, nf_max, 0) <= (size_t)lds_max) {
+        lds_rg = rg;
+      }
+    }
+    if (!lds_rg) return create_fail(GALSAT_EUNSUPPORTED, "a formula is too large for the LDS schedule");
+  }
   int32_t krec;
   if (opt.partials == GALSAT_PARTIALS_STORE) krec = -1;           // every clause stores
   else if (opt.partials == GALSAT_PARTIALS_RECOMPUTE) krec = kmax;
   else krec = opt.recompute_max_len > 0 ? opt.recompute_max_len : kDefaultRecomputeMaxLen;
   if (krec_o >= -1 && opt.plan_override && std::strstr(opt.plan_override, "krec=")) krec = krec_o;
+  if (lds_rg) krec = kmax;
   h->ld = (int32_t)round_up(R, 4);
   h->ldD = round_up(R, 4);
   h->stream_items = stream_o >= 0 ? stream_o : 0;
@@ -602,7 +655,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   if (h->two_phase && opt.workspace_budget_bytes > 0 &&
       (size_t)L * (size_t)h->ldD * sizeof(float) > opt.workspace_budget_bytes)
     h->two_phase = 0;
-  if (h->stream_items) h->two_phase = 0;
+  if (h->stream_items || lds_rg) h->two_phase = 0;
   // chunks per formula of the XCD-aware order (several formulas per launch)
   const int64_t xcd_chunks =
       xcdc_o >= 0 ? xcdc_o : (h->two_phase ? kXcdChunksTwoPhase : kXcdChunks);
@@ -1089,7 +1142,14 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   }
   std::vector<int32_t> fnone(F, 0);
   // schedule
-  h->schedule = opt.schedule == GALSAT_SCHED_PLAIN ? GALSAT_SCHED_PLAIN : GALSAT_SCHED_GENERAL;
+  h->schedule = opt.schedule == GALSAT_SCHED_PLAIN ? GALSAT_SCHED_PLAIN
+              : lds_rg                                ? GALSAT_SCHED_LDS
+                                                      : GALSAT_SCHED_GENERAL;
+  h->lds_rg = lds_rg;
+  h->lds_stage = lds_stage;
+  h->lds_nocc = lds_nocc;
+  h->nf_max = 0;
+  for (int32_t f = 0; f < F; ++f) h->nf_max = std::max(h->nf_max, fvb[f + 1] - fvb[f]);
 
   // ---- device upload and workspace
   galsat_ctx* c = h.get();
@@ -1674,6 +1734,7 @@ extern "C" galsat_status galsat_step_prepare(galsat_handle h, float* x, int32_t 
   if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
   if (steps <= 0) return h->fail(GALSAT_EINVAL, "steps must be >= 1");
   (void)opt_state;
+  if (h->lds_rg) return GALSAT_OK;  // galsat_step is one launch already
   if (!h->opt.use_graph || h->opt.optimizer == GALSAT_OPT_ADAM || h->prof)
     return h->fail(GALSAT_EUNSUPPORTED, "this handle runs galsat_step eagerly");
   return capture_steps(h, h->tile, x, ldx, steps, loss_trace, unsat_trace);
@@ -1695,6 +1756,16 @@ extern "C" galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, flo
   // the internal state is aligned for the planned tile; the caller's Adam
   // moments may not be
   const Tile t = adam ? tile_for(h, mom, ldx, vel, ldx) : h->tile;
+  if (h->lds_rg) {
+    // every step in one persistent launch, the state read and written once
+    PersistArgs pa{h->var_ptr, h->occ4, h->occx, h->clause_ptr, h->clause_lits, h->f_vbeg,
+                   h->n_empty, x, ldx, h->R, h->F, steps, h->nf_max, h->lds_nocc, h->lds_stage,
+                   h->opt.lr, loss_trace,
+                   unsat_trace};
+    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+    GS_HIP(h, launch_persistent(pa, h->lds_rg, s), "persistent step loop");
+    return GALSAT_OK;
+  }
   if (h->opt.use_graph && !adam && !h->prof) {
     galsat_status st = capture_steps(h, t, x, ldx, steps, loss_trace, unsat_trace);
     if (st != GALSAT_OK) return st;

@@ -111,6 +111,32 @@ struct FinalizeArgs {
   int32_t max_rows;             // most partial rows of one formula (host value; caps split)
 };
 
+// Persistent LDS schedule: one workgroup per (formula, restart group) runs
+// every step with the group's state in LDS (galsat_persist.hip).
+constexpr int kPersistBlock = 512;
+struct PersistArgs {
+  const int32_t* var_ptr;
+  const int4* occ;              // occurrence records (every clause recomputed)
+  const int4* occx;
+  const int32_t* clause_ptr;
+  const int32_t* clause_lits;
+  const int32_t* f_vbeg;        // [F+1]
+  const int32_t* n_empty;       // [F]
+  float* x;                     // caller's state [n][ldx], read at the start, written at the end
+  int32_t ldx;
+  int32_t R;
+  int32_t F;
+  int32_t steps;
+  int32_t nf_max;               // most variables of one formula
+  int32_t nocc_max;             // most occurrences of one formula
+  int32_t stage_occ;            // 1: records and var_ptr slice copied to LDS per launch
+  float lr;
+  float* loss_trace;            // [steps][F][R] or null
+  int32_t* unsat_trace;
+};
+size_t persist_lds_bytes(int rg, int nf_max, int nocc_stage);
+hipError_t launch_persistent(const PersistArgs& a, int rg, hipStream_t s);
+
 // Workspace of the split finalize: entries of part_l and part_u.
 constexpr int64_t kFinalizeScratch = 1024 * 64;
 

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libgalsat.so")
 
 OPT = {"sgd": 0, "sgd_clamp": 0, "adam": 1}
 PARTIALS = {"auto": 0, "store": 1, "recompute": 2}
-SCHEDULE = {"auto": 0, "general": 1, "plain": 3}
+SCHEDULE = {"auto": 0, "general": 1, "lds": 2, "plain": 3}
 SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
 
 _P = ctypes.c_void_p

@@ -296,6 +296,58 @@ def test_degenerate_formulas(clauses, n, R):
         check_update(x1, oracle.step_sgd(xr, g_ref, prob.lr), xr, R, "degenerate step")
 
 
+@pytest.mark.parametrize("case", ["planted300", "edge", "small_batch"])
+@pytest.mark.parametrize("R", [1, 7, 16, 40])
+def test_lds_schedule_matches_general(case, R):
+    """The persistent LDS schedule forms the same products and sums them in
+    the same order as the general single pass with recomputed partials:
+    states and counts bitwise, loss allclose; and parity with the oracle."""
+    say(f"[lds] {case} R={R}")
+    if case == "small_batch":
+        cnf = I.concat([I.planted_ksat(30 + 11 * i, 4 * (30 + 11 * i), 3, seed=600 + i)
+                        for i in range(9)] + [I.from_clauses([[]], n=1),
+                                              I.from_clauses([[1, 2], [-1, 2], [1, -2], [-1, -2]], n=2)])
+    else:
+        cnf = CASES[case]()
+    a = Problem(cnf, R, schedule="lds", lr=0.1)
+    assert a.info()["schedule"] == "lds"
+    b = Problem(cnf, R, schedule="general", partials="recompute", lr=0.1, plan_override="two=0")
+    x = _x0(cnf.n, R, 91)
+    xa, xb = x.clone(), x.clone()
+    la, ua = a.step(xa, 25, trace=True)
+    lb, ub = b.step(xb, 25, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb)
+    assert torch.equal(ua, ub)
+    assert torch.allclose(la, lb, rtol=1e-6, atol=1e-30)
+    # records read from global memory, and other restart groups: same states
+    for pb in ("ldsstage=0", "ldsrg=8,ldsstage=0", "ldsrg=1"):
+        c = Problem(cnf, R, schedule="lds", lr=0.1, plan_override=pb)
+        xc = x.clone()
+        lc, uc = c.step(xc, 25, trace=True)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xc), pb
+        assert torch.equal(ua, uc), pb
+        assert torch.allclose(la, lc, rtol=1e-6, atol=1e-30), pb
+    parity_at(a, cnf, xa, f"lds {case} R={R}")
+    # one more step from there against the oracle (teacher forced)
+    xr = to_oracle(xa, R)
+    _, g_ref, _ = oracle.grad(cnf, xr, with_abs=True)
+    x1 = xa.clone()
+    lt, ut = a.step(x1, 1, trace=True)
+    torch.cuda.synchronize()
+    check_counts(ut[0], oracle.unsat(cnf, xr), "lds step trace")
+
+
+def test_lds_schedule_limits():
+    from paper_2603_28796_amd.galsat import GalsatError
+    say("[lds] limits")
+    with pytest.raises(GalsatError):
+        Problem(CASES["mixed20k"](), 16, schedule="lds")            # too many variables
+    with pytest.raises(GalsatError):
+        Problem(CASES["planted300"](), 16, schedule="lds", optimizer="adam")
+
+
 def test_unaligned_and_padded_state():
     say("[layout] padded and odd row strides")
     cnf = CASES["planted300"]()
