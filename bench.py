@@ -233,6 +233,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel run")
     ap.add_argument("--graph", type=int, default=1, help="replay the step loop from a hipGraph")
+    ap.add_argument("--schedule", default="auto", help="auto | general | lds | plain")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the batched vs one-formula-at-a-time comparison (0: skip)")
     ap.add_argument("--gumbel-steps", type=int, default=50,
@@ -271,7 +272,7 @@ def main():
     partials = args.partials or {0: "auto", 1: "store", 2: "recompute"}[w.recompute]
     torch.cuda.set_device(0)
     prob = Problem(cnf, R, lr=w.lr, partials=partials, plan_override=args.plan,
-                   use_graph=bool(args.graph))
+                   use_graph=bool(args.graph), schedule=args.schedule)
     info = prob.info()
     log(f"[bench] plan: {info}")
     x = prob.init_state(I.SEED_BASE + 2)
@@ -325,7 +326,9 @@ def main():
         prob.profile(False)
         log(f"[bench] kernel times: {kernels}")
         launches, tot = kernels.get("var_pass", (0, 0.0))
-        if launches:
+        # the LDS schedule runs every step in one launch with the state held
+        # in LDS between steps: no per-step HBM roofline applies to it
+        if launches and info["schedule"] != "lds":
             # the pass may be split into several launches per step (restart
             # tile groups): each launch moves its share of the step's bytes
             per_step = launches / K
@@ -375,7 +378,7 @@ def main():
         "config": {"workload": w.key + (f"/width{args.tseitin}" if args.tseitin else ""),
                    "description": w.description, "n": cnf.n, "m": cnf.m,
                    "L": cnf.L, "formulas": cnf.F, "restarts": R, "lr": w.lr, "partials": partials,
-                   "lanes_per_item": info["lanes_per_item"],
+                   "schedule": info["schedule"], "lanes_per_item": info["lanes_per_item"],
                    "restarts_per_lane": info["restarts_per_lane"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -198,3 +198,57 @@ def test_planning_degenerate_formulas(clauses, n):
             G.load_library().galsat_destroy(h)
         else:
             assert st == -3, (R, msg)
+
+
+def _create_with(cnf, R, plan=None, **fields):
+    """galsat_create with option fields set; returns (status, message)."""
+    lib = G.load_library()
+    arrs = {k: np.ascontiguousarray(getattr(cnf, k), dtype=np.int32) for k in
+            ("formula_var_begin", "formula_clause_begin", "clause_ptr", "clause_lits", "var_ptr",
+             "var_occ")}
+    prob = G._Problem(cnf.F, arrs["formula_var_begin"].ctypes.data,
+                      arrs["formula_clause_begin"].ctypes.data, cnf.n, cnf.m, cnf.L,
+                      arrs["clause_ptr"].ctypes.data, arrs["clause_lits"].ctypes.data,
+                      arrs["var_ptr"].ctypes.data, arrs["var_occ"].ctypes.data, R, 0)
+    opt = G._Options()
+    lib.galsat_default_options(ctypes.byref(opt))
+    for k, v in fields.items():
+        setattr(opt, k, v)
+    keep = plan.encode() if plan else None
+    opt.plan_override = keep
+    h = ctypes.c_void_p()
+    st = lib.galsat_create(ctypes.byref(prob), ctypes.byref(opt), None, ctypes.byref(h))
+    msg = lib.galsat_last_error(None).decode()
+    if st == 0:
+        lib.galsat_destroy(h)
+    return st, msg
+
+
+@pytest.mark.parametrize("plan", ["", "ldsrg=1", "ldsrg=32", "ldsstage=0", "ldsrg=8,ldsstage=0"])
+def test_lds_schedule_planning(plan):
+    """The persistent LDS schedule plans uneven batches with empty clauses
+    and clauses of up to 80 literals (records that name their clause) for
+    every restart group and with the records staged or not: planning gets
+    as far as the first upload without a GPU."""
+    fs = [I.planted_ksat(30 + 7 * i, 4 * (30 + 7 * i), 3, seed=500 + i) for i in range(5)]
+    fs.append(I.from_clauses([[]], n=1))
+    fs.append(I.generate(I.spec(2, k0=3, ka=20, kb=80, p0=0.8, var_kind=1, zipf_s=1.2),
+                         21, [400], [500], "long"))
+    cnf = I.concat(fs, name="plan")
+    for R in (1, 16, 40):
+        for partials in (0, 2):
+            st, msg = _create_with(cnf, R, plan, schedule=G.SCHEDULE["lds"], partials=partials)
+            assert st in (0, -3), (R, partials, msg)
+
+
+def test_lds_schedule_rejections():
+    """Adam, stored partials and a formula whose state does not fit LDS
+    (12 bytes per variable of one restart within 64 KB: about 5,400
+    variables) are refused as unsupported, before any device call."""
+    lds = G.SCHEDULE["lds"]
+    small = I.planted_ksat(100, 400, 3, seed=7)
+    assert _create_with(small, 16, schedule=lds, optimizer=1)[0] == -5
+    assert _create_with(small, 16, schedule=lds, partials=G.PARTIALS["store"])[0] == -5
+    assert _create_with(I.planted_ksat(5400, 21600, 3, seed=8), 4, schedule=lds)[0] in (0, -3)
+    st, msg = _create_with(I.planted_ksat(5500, 22000, 3, seed=9), 4, schedule=lds)
+    assert st == -5 and "too large" in msg
