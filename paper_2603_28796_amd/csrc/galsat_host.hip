@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
@@ -620,13 +621,20 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     // largest formula keeps its own slot of the 512 threads (a step makes
     // one pass over the variables).  Fewer when the state does not fit.
     // The records are staged when they fit beside it.
+    // A dispatch holds fewer than 2^32 work-items per dimension, so very
+    // large batches take bigger groups (several passes over the variables)
+    // or are refused.
+    auto items = [&](int g) { return (int64_t)F * ((R + g - 1) / g) * kPersistBlock; };
     int rg = 1;
     while (rg < 32 && rg < R && (int64_t)(kPersistBlock / (2 * rg)) >= nf_max &&
            (int64_t)F * ((R + rg - 1) / rg) > kPersistSpreadGroups)
       rg *= 2;
     if (ldsrg_o == 1 || ldsrg_o == 2 || ldsrg_o == 4 || ldsrg_o == 8 || ldsrg_o == 16 || ldsrg_o == 32)
       rg = ldsrg_o;
-    for (; rg >= 1 && !lds_rg; rg /= 2) {
+    while (rg < 32 && items(rg) > (int64_t)UINT32_MAX) rg *= 2;
+    if (items(rg) > (int64_t)UINT32_MAX)
+      return create_fail(GALSAT_EUNSUPPORTED, "too many formulas x restarts for the LDS schedule");
+    for (; rg >= 1 && !lds_rg && items(rg) <= (int64_t)UINT32_MAX; rg /= 2) {
       if (ldsstage_o != 0 && persist_lds_bytes(rg, nf_max, lds_nocc) <= (size_t)lds_max) {
         lds_rg = rg;
         lds_stage = 1;

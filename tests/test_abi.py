@@ -252,3 +252,16 @@ def test_lds_schedule_rejections():
     assert _create_with(I.planted_ksat(5400, 21600, 3, seed=8), 4, schedule=lds)[0] in (0, -3)
     st, msg = _create_with(I.planted_ksat(5500, 22000, 3, seed=9), 4, schedule=lds)
     assert st == -5 and "too large" in msg
+
+
+def test_lds_schedule_dispatch_limit():
+    """A dispatch holds fewer than 2^32 work-items: 200 formulas at 65,536
+    restarts still plan (two restarts per workgroup); 5,000 one-variable
+    formulas at 65,536 restarts need more than 32 per workgroup and are
+    refused."""
+    lds = G.SCHEDULE["lds"]
+    mid = I.concat([I.planted_ksat(300, 1200, 3, seed=900 + i) for i in range(200)], name="mid")
+    assert _create_with(mid, 65536, schedule=lds)[0] in (0, -3)
+    tiny = I.concat([I.from_clauses([[1]], n=1)] * 5000, name="tiny")
+    st, msg = _create_with(tiny, 65536, schedule=lds)
+    assert st == -5 and "too many" in msg
