@@ -339,6 +339,32 @@ def test_lds_schedule_matches_general(case, R):
     check_counts(ut[0], oracle.unsat(cnf, xr), "lds step trace")
 
 
+@pytest.mark.parametrize("case", ["edge", "batch", "long_mix", "planted300"])
+@pytest.mark.parametrize("R", [5, 64])
+def test_lds_schedule_steps_against_oracle(case, R):
+    """Each step of the persistent LDS schedule against the oracle, teacher
+    forced from the GPU's state: the loss and unsat trace entries at x_k
+    and the projected-SGD update x_k+1, over three steps. The cases have
+    clauses of up to 200 literals (records that name their clause or carry
+    extension records), Zipf-heavy variables (split in the general plan,
+    not here), an empty clause and formulas of 2 to 5,000 variables."""
+    say(f"[lds-oracle] {case} R={R}")
+    cnf = CASES[case]()
+    prob = Problem(cnf, R, schedule="lds", lr=0.1)
+    assert prob.info()["schedule"] == "lds"
+    x = _x0(cnf.n, R, 73)
+    for k in range(3):
+        xr = to_oracle(x, R)
+        lo_ref, g_ref, _ = oracle.grad(cnf, xr, with_abs=True)
+        x1 = x.clone()
+        lt, ut = prob.step(x1, 1, trace=True)
+        torch.cuda.synchronize()
+        check_loss(lt[0], lo_ref, cnf, f"lds {case} R={R} step {k}")
+        check_counts(ut[0], oracle.unsat(cnf, xr), f"lds {case} R={R} step {k}")
+        check_update(x1, oracle.step_sgd(xr, g_ref, prob.lr), xr, R, f"lds {case} R={R} step {k}")
+        x = x1
+
+
 def test_lds_schedule_limits():
     from paper_2603_28796_amd.galsat import GalsatError
     say("[lds] limits")
