@@ -159,7 +159,8 @@ typedef struct {
                               0: off), segdiv (heavy-variable split divisor), ldsrg
                               (LDS schedule: restarts per workgroup, 1, 2, 4, 8, 16 or
                               32), ldsstage (0: the LDS schedule reads the records from
-                              global memory).  Keys left out take the plan's own
+                              global memory), ldslpt (0: the LDS schedule issues
+                              formulas in index order, not LPT order).  Keys left out take the plan's own
                               choice. */
 } galsat_options;
 

@@ -189,6 +189,7 @@ struct galsat_ctx {
   // (loss only, round check) count them themselves and add zero_empty.
   int32_t *n_empty = nullptr, *zero_empty = nullptr;
   int32_t *f_vbeg = nullptr, *f_cbeg = nullptr;
+  int32_t* lds_order = nullptr;  // formulas of the LDS schedule, costliest first
   // workspace
   float *D = nullptr, *xa = nullptr, *xb = nullptr;
   float* nbuf = nullptr;  // noise of the straight-through Gumbel mode (allocated on first use)
@@ -381,10 +382,12 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // wave (0: no wave-per-clause pass), short (0: no short-clause pass), xseq
 // (one formula: about this many chunks in an XCD-contiguous order), segdiv,
 // ldsrg (restarts per workgroup of the LDS schedule: 1, 2, 4, 8, 16 or 32)
-// and ldsstage (0: the LDS schedule reads records from global memory).
+// ldsstage (0: the LDS schedule reads records from global memory) and
+// ldslpt (0: the LDS schedule issues formulas in index order).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
                     int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
-                    int* short_clauses, int* xseq, int* segdiv, int* ldsrg, int* ldsstage) {
+                    int* short_clauses, int* xseq, int* segdiv, int* ldsrg, int* ldsstage,
+                    int* ldslpt) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -411,6 +414,7 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "segdiv") *segdiv = v;
       else if (k == "ldsrg") *ldsrg = v;
       else if (k == "ldsstage") *ldsstage = v;
+      else if (k == "ldslpt") *ldslpt = v;
     }
     pos = comma + 1;
   }
@@ -593,9 +597,10 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // ---- plan: which clauses recompute their partials in the variable pass
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
   int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1, segdiv_o = -1;
-  int ldsrg_o = 0, ldsstage_o = -1;
+  int ldsrg_o = 0, ldsstage_o = -1, ldslpt_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
-                 &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o, &ldsrg_o, &ldsstage_o);
+                 &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o, &ldsrg_o, &ldsstage_o,
+                 &ldslpt_o);
   const bool csort = csort_o != 0;
   // Persistent LDS schedule: every formula's restart group must fit in LDS
   // (state double-buffered); SGD only; every clause recomputed.
@@ -1277,6 +1282,18 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(zero_empty, fnone);
   UP(f_vbeg, fvb);
   UP(f_cbeg, fcb);
+  // LDS schedule: formulas in LPT order (most occurrences first, ties by
+  // id), so the longest workgroups start first and the tail is short
+  std::vector<int32_t> lds_order;
+  if (lds_rg) {
+    lds_order.resize((size_t)F);
+    for (int32_t f = 0; f < F; ++f) lds_order[f] = f;
+    if (ldslpt_o != 0)
+      std::stable_sort(lds_order.begin(), lds_order.end(), [&](int32_t p, int32_t q) {
+        return vp[fvb[p + 1]] - vp[fvb[p]] > vp[fvb[q + 1]] - vp[fvb[q]];
+      });
+  }
+  UP(lds_order, lds_order);
   if (two) AL(D, (size_t)std::max<int64_t>(L, 1) * (size_t)c->ldD);  // one row per slot
   else if (stored > 0) AL(D, (size_t)stored * (size_t)c->ldD);
   AL(xa, (size_t)n * c->ld);
@@ -1767,7 +1784,7 @@ extern "C" galsat_status galsat_step(galsat_handle h, float* x, int32_t ldx, flo
   if (h->lds_rg) {
     // every step in one persistent launch, the state read and written once
     PersistArgs pa{h->var_ptr, h->occ4, h->occx, h->clause_ptr, h->clause_lits, h->f_vbeg,
-                   h->n_empty, x, ldx, h->R, h->F, steps, h->nf_max, h->lds_nocc, h->lds_stage,
+                   h->lds_order, h->n_empty, x, ldx, h->R, h->F, steps, h->nf_max, h->lds_nocc, h->lds_stage,
                    h->opt.lr, loss_trace,
                    unsat_trace};
     ProfScope _ps(h, GALSAT_K_VAR_PASS, s);

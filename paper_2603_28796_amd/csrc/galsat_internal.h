@@ -121,6 +121,7 @@ struct PersistArgs {
   const int32_t* clause_ptr;
   const int32_t* clause_lits;
   const int32_t* f_vbeg;        // [F+1]
+  const int32_t* f_order;       // [F] formula of each workgroup row (LPT order)
   const int32_t* n_empty;       // [F]
   float* x;                     // caller's state [n][ldx], read at the start, written at the end
   int32_t ldx;

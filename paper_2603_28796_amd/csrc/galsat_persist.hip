@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(PersistArgs a) {
   float* xa = reinterpret_cast<float*>(smem + lay.x);
   float* xb = xa + (int64_t)a.nf_max * RG;
   const int groups = (a.R + RG - 1) / RG;
-  const int f = blockIdx.x / groups, grp = blockIdx.x % groups;
+  const int f = a.f_order[blockIdx.x / groups], grp = blockIdx.x % groups;
   const int lane = threadIdx.x % RG, slot = threadIdx.x / RG;
   const int wave = threadIdx.x / 64, wlane = threadIdx.x % 64;
   const int r = grp * RG + lane;
