@@ -142,9 +142,16 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(PersistArgs a) {
       if constexpr (STAGED) recs = s_occ;
       else recs = a.occ + qb;
       const int self = (vb + vi) << 1;  // a code whose state row is in LDS
-      int q = q0;
-      for (; q + 4 <= q1; q += 4) {  // four records in flight
-        const int4 o[4] = {recs[q], recs[q + 1], recs[q + 2], recs[q + 3]};
+      // four records in flight; a partial last batch re-reads its last
+      // record and masks the extra contributions off
+      for (int q = q0; q < q1; q += 4) {
+        int4 o[4];
+        bool ok[4];
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+          ok[k2] = q + k2 < q1;
+          o[k2] = recs[ok[k2] ? q + k2 : q1 - 1];
+        }
         bool short3 = true;
 #pragma unroll
         for (int k2 = 0; k2 < 4; ++k2)
@@ -159,13 +166,14 @@ __global__ __launch_bounds__(kPersistBlock) void k_persistent(PersistArgs a) {
             y[k2][2] = lds_row<RG>(xa, vb, nother > 2 ? o[k2].w : self, lane);
           }
 #pragma unroll
-          for (int k2 = 0; k2 < 4; ++k2) add3(o[k2], y[k2]);
+          for (int k2 = 0; k2 < 4; ++k2)
+            if (ok[k2]) add3(o[k2], y[k2]);
         } else {
 #pragma unroll
-          for (int k2 = 0; k2 < 4; ++k2) add(o[k2], q + k2);
+          for (int k2 = 0; k2 < 4; ++k2)
+            if (ok[k2]) add(o[k2], q + k2);
         }
       }
-      for (; q < q1; ++q) add(recs[q], q);
       xb[vi * RG + lane] = clamp01((double)xv - (double)a.lr * g);
     }
     // fixed-order reduction over the slots of each restart: butterflies over
