@@ -304,7 +304,9 @@ galsat_status galsat_set_adam_step(galsat_handle h, int32_t t);
  * per item and restarts per lane), the clause-length histogram (recompute
  * threshold when clauses longer than 8 literals exist), the formula
  * count (chunks per formula of the XCD-aware order) and, for at most 64
- * restarts, single pass against two-phase gradient; creates a handle for
+ * restarts, single pass against two-phase gradient; with the LDS schedule
+ * instead its restarts per workgroup (1 to 32, up to the restarts rounded
+ * to a power of two), records staged or not; creates a handle for
  * each, times `steps` steps of galsat_step from a copy of x0 with HIP
  * events on `stream`, and writes the fastest plan as a plan_override string
  * to plan_out (host, plan_cap >= 64 bytes) and its time per step to

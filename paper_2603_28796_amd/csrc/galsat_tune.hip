@@ -141,6 +141,13 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
     for (const auto& k : krecs)
       for (const auto& x : xcd)
         for (const auto& w : twos) plans.push_back(t + k + x + w);
+  if (base.schedule == GALSAT_SCHED_LDS) {
+    // the persistent schedule has its own choices: restarts per workgroup
+    // (up to the restarts rounded to a power of two) and record staging
+    plans.clear();
+    for (int g = 1; g <= 32 && g < 2 * R; g *= 2)
+      for (const char* st : {"", ",ldsstage=0"}) plans.push_back("ldsrg=" + std::to_string(g) + st);
+  }
   for (const auto& plan : plans) {
     galsat_options o = base;
     o.plan_override = plan.c_str();

@@ -365,6 +365,25 @@ def test_lds_schedule_steps_against_oracle(case, R):
         x = x1
 
 
+def test_lds_schedule_autotune():
+    """Under the LDS schedule the autotuner chooses among restart groups and
+    record staging, and the chosen plan keeps oracle parity."""
+    from paper_2603_28796_amd.galsat import autotune
+    say("[lds] autotune")
+    cnf = CASES["planted300"]()
+    R = 40
+    x0 = _x0(cnf.n, R, 5)
+    plan, ms = autotune(cnf, R, x0, steps=3, schedule="lds")
+    assert plan.startswith("ldsrg=") and ms > 0, plan
+    prob = Problem(cnf, R, schedule="lds", lr=0.1, plan_override=plan)
+    x = x0.clone()
+    xr = to_oracle(x, R)
+    _, g_ref, _ = oracle.grad(cnf, xr, with_abs=True)
+    prob.step(x, 1)
+    torch.cuda.synchronize()
+    check_update(x, oracle.step_sgd(xr, g_ref, prob.lr), xr, R, f"lds autotuned {plan}")
+
+
 def test_lds_schedule_limits():
     from paper_2603_28796_amd.galsat import GalsatError
     say("[lds] limits")
