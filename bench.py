@@ -379,6 +379,8 @@ def main():
                    "description": w.description, "n": cnf.n, "m": cnf.m,
                    "L": cnf.L, "formulas": cnf.F, "restarts": R, "lr": w.lr, "partials": partials,
                    "schedule": info["schedule"], "lanes_per_item": info["lanes_per_item"],
+                   **({"lds_restarts_per_group": info["lds_restarts_per_group"],
+                       "lds_staged": info["lds_staged"]} if info["schedule"] == "lds" else {}),
                    "restarts_per_lane": info["restarts_per_lane"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

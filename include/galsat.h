@@ -332,6 +332,8 @@ typedef struct {
   int32_t xseq_chunks;          /* chunks of the XCD-contiguous order of one formula, 0: off */
   size_t device_bytes;          /* device memory held by the handle */
   int32_t adam_step;
+  int32_t lds_restarts_per_group; /* LDS schedule: restarts per workgroup, 0: not used */
+  int32_t lds_staged;           /* LDS schedule: 1 when the records are copied to LDS */
 } galsat_info;
 
 galsat_status galsat_get_info(galsat_handle h, galsat_info* info);

@@ -1352,6 +1352,8 @@ extern "C" galsat_status galsat_get_info(galsat_handle h, galsat_info* info) {
   info->xseq_chunks = h->xseq;
   info->device_bytes = h->device_bytes;
   info->adam_step = h->adam_t;
+  info->lds_restarts_per_group = h->lds_rg;
+  info->lds_staged = h->lds_stage;
   return GALSAT_OK;
 }
 

@@ -71,6 +71,7 @@ class _Info(ctypes.Structure):
         ("stored_lits", ctypes.c_int64), ("schedule", _I32), ("lanes_per_item", _I32),
         ("restarts_per_lane", _I32), ("var_chunks", _I32), ("clause_chunks", _I32),
         ("two_phase", _I32), ("xseq_chunks", _I32), ("device_bytes", ctypes.c_size_t), ("adam_step", _I32),
+        ("lds_restarts_per_group", _I32), ("lds_staged", _I32),
     ]
 
 

@@ -310,7 +310,10 @@ def test_lds_schedule_matches_general(case, R):
     else:
         cnf = CASES[case]()
     a = Problem(cnf, R, schedule="lds", lr=0.1)
-    assert a.info()["schedule"] == "lds"
+    info = a.info()
+    assert info["schedule"] == "lds"
+    # at most 512 workgroups: one restart each; the records fit LDS here
+    assert info["lds_restarts_per_group"] == 1 and info["lds_staged"] == 1, info
     b = Problem(cnf, R, schedule="general", partials="recompute", lr=0.1, plan_override="two=0")
     x = _x0(cnf.n, R, 91)
     xa, xb = x.clone(), x.clone()
