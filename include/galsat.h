@@ -160,7 +160,10 @@ typedef struct {
                               (LDS schedule: restarts per workgroup, 1, 2, 4, 8, 16 or
                               32), ldsstage (0: the LDS schedule reads the records from
                               global memory), ldslpt (0: the LDS schedule issues
-                              formulas in index order, not LPT order).  Keys left out take the plan's own
+                              formulas in index order, not LPT order), xpin (1: the
+                              single pass maps restart tiles to XCDs by linear block
+                              id, 0: off; on by default for one formula with at least
+                              1,024 restarts).  Keys left out take the plan's own
                               choice. */
 } galsat_options;
 

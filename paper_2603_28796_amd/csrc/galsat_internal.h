@@ -44,6 +44,7 @@ struct VarPassArgs {
   int32_t chunk_base;           // first chunk of this launch
   int32_t tile_base;            // first restart tile of this launch
   int32_t tile_count;           // restart tiles of this launch (0: all from tile_base)
+  int32_t xcd_pin;              // 1: the single pass maps tiles to XCDs (see k_var_pass)
   int32_t stream_items;         // 1: walk each slot's variables as one occurrence list
   const int32_t* occ_own;       // [L] own variable of each slot (two-phase plan)
   const int32_t* var_perm;      // [n] variable processed as the i-th item of the variable

@@ -168,10 +168,18 @@ __global__ __launch_bounds__(kBlock) void k_var_pass(VarPassArgs a) {
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
   const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;
-  const int chunk =
-      a.chunk_order ? ldc(a.chunk_order, a.chunk_base + blockIdx.x) : a.chunk_base + blockIdx.x;
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (a.xcd_pin) {
+    // tile = linear block id mod tiles: workgroups are dealt to the 8 XCDs
+    // round-robin in that order, so with 8 tiles per launch an XCD's L2
+    // serves one tile's lines only
+    const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+    by = lin % gridDim.y;
+    bx = lin / gridDim.y;
+  }
+  const int chunk = a.chunk_order ? ldc(a.chunk_order, a.chunk_base + bx) : a.chunk_base + bx;
   if (chunk < 0) return;  // padding of the XCD-aware order: the whole block leaves
-  const int tile = a.tile_base + blockIdx.y;
+  const int tile = a.tile_base + by;
   const int r0 = tile * RT + lane * RPL;
   const bool active = r0 < a.R;
   const int rc = active ? r0 : 0;  // in-bounds column for lanes past the last restart

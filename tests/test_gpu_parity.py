@@ -387,6 +387,25 @@ def test_lds_schedule_autotune():
     check_update(x, oracle.step_sgd(xr, g_ref, prob.lr), xr, R, f"lds autotuned {plan}")
 
 
+@pytest.mark.parametrize("plan", ["lpi=8,rpl=1,tg=8", "lpi=16,rpl=4,tg=8", "lpi=64,rpl=4,tg=2"])
+def test_xcd_pinned_tiles(plan):
+    """Restart tiles mapped to XCDs by linear block id (xpin=1) run the same
+    (chunk, tile) pairs as the plain grid: states, counts and loss bitwise
+    equal to the unpinned plan, and parity with the oracle."""
+    say(f"[xpin] {plan}")
+    cnf = CASES["planted300"]()
+    R = 512 if "rpl=4" in plan else 64
+    a = Problem(cnf, R, lr=0.1, plan_override=plan + ",two=0,xpin=1")
+    b = Problem(cnf, R, lr=0.1, plan_override=plan + ",two=0")
+    x = _x0(cnf.n, R, 29)
+    xa, xb = x.clone(), x.clone()
+    la, ua = a.step(xa, 5, trace=True)
+    lb, ub = b.step(xb, 5, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb) and torch.equal(ua, ub) and torch.equal(la, lb)
+    parity_at(a, cnf, xa, f"xpin {plan}")
+
+
 def test_lds_schedule_limits():
     from paper_2603_28796_amd.galsat import GalsatError
     say("[lds] limits")
