@@ -31,6 +31,11 @@ MUTANTS = {
     "sgd_no_upper_clamp": ("    if (y > 1.0) y = 1.0;\n    x[i] = y;\n  }\n}\n\n/* Adam",
                            "    x[i] = y;\n  }\n}\n\n/* Adam"),
     "def_mode_includes_self": ("if (i != j) others *= factor(c[i], xr);", "others *= factor(c[i], xr);"),
+    "full_step_counts_after_update": (
+        "  oracle_unsat(n, F, fcb, cptr, lits, R, x, unsat);\n  oracle_grad(n, F, fcb, cptr, lits, R, x, loss, grad, NULL);\n  oracle_step_sgd((int64_t)R * n, lr, x, grad);",
+        "  oracle_grad(n, F, fcb, cptr, lits, R, x, loss, grad, NULL);\n  oracle_step_sgd((int64_t)R * n, lr, x, grad);\n  oracle_unsat(n, F, fcb, cptr, lits, R, x, unsat);"),
+    "full_step_half_rate": ("oracle_step_sgd((int64_t)R * n, lr, x, grad);\n}",
+                            "oracle_step_sgd((int64_t)R * n, 0.5 * lr, x, grad);\n}"),
     "empty_product_zero": ("  double u = 1.0;\n  for (int32_t i = 0; i < k; ++i) u *= factor",
                            "  double u = (k == 0) ? 0.0 : 1.0;\n  for (int32_t i = 0; i < k; ++i) u *= factor"),
 }
@@ -53,6 +58,7 @@ def _pins():
         lambda: P.test_unsat_count_with_ties_at_half(),
         lambda: P.test_best_is_first_minimum(),
         lambda: P.test_batch_equals_formulas_alone(),
+        lambda: P.test_full_step_matches_autograd_sgd_and_boolean_count(),
         lambda: Gp.test_step_matches_two_logit_autograd(True, 1.0),
         lambda: Gp.test_step_matches_two_logit_autograd(False, 0.5),
         lambda: Gp.test_tie_goes_to_state_zero(),

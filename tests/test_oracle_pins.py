@@ -399,3 +399,38 @@ def test_init_state_is_uniform_on_a_24bit_grid():
     assert len(np.unique(x)) > 0.99 * x.size
     # different seeds give different states
     assert not np.array_equal(x, oracle.init_state(0x6A150002, 500, 64))
+
+
+# --- the full iteration timed as the CPU baseline --------------------------------
+
+def test_full_step_matches_autograd_sgd_and_boolean_count():
+    """One full iteration (Section 3.2): loss' of Eq. (2)/(5) and its gradient
+    from torch autograd, the projected update from torch.optim.SGD followed
+    by the clamp, and the unsat count of round(x) at the state before the
+    update by direct Boolean evaluation."""
+    rng = np.random.default_rng(41)
+    n = 11
+    clauses = _random_clauses(rng, n, 45, 1, 6)
+    clauses += [[2, 2, -7], [3, -3], []]
+    cnf = _cnf(clauses, n)
+    x = rng.random((4, n))
+    x[0, :3] = [0.5, 0.0, 1.0]          # a rounding tie and clamped values
+    x[1] = rng.integers(0, 2, size=n)   # a 0/1 point
+    lr = 0.37
+    lo, us, g, x1 = oracle.full_step(cnf, x, lr)
+    xt = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    L = _torch_loss(clauses, xt)
+    L.sum().backward()
+    np.testing.assert_allclose(lo[0], L.detach().numpy(), rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(g, xt.grad.numpy(), rtol=1e-12, atol=1e-14)
+    p = torch.nn.Parameter(torch.tensor(x))
+    opt = torch.optim.SGD([p], lr=lr)
+    p.grad = xt.grad.clone()
+    opt.step()
+    with torch.no_grad():
+        p.clamp_(0.0, 1.0)
+    np.testing.assert_allclose(x1, p.detach().numpy(), rtol=0, atol=1e-14)
+    for r in range(x.shape[0]):
+        assert us[0, r] == _bool_unsat(clauses, (x[r] > 0.5).astype(int))
+    # at the 0/1 point the loss is the Boolean count itself
+    assert lo[0, 1] == float(us[0, 1])
