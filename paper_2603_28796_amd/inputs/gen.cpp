@@ -247,7 +247,21 @@ int gen_transpose(int32_t F, const int64_t* var_begin, const int64_t* clause_beg
   const int64_t n = var_begin[F];
   const int64_t L = clause_ptr[clause_begin[F]];
   std::vector<int32_t> cnt((size_t)n + 1, 0);
+  // per-formula threads are race-free only while every literal names a
+  // variable of its own formula; otherwise threads own variable ranges
+  int bad = 0;
   if (F > 1) {
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int32_t f = 0; f < F; ++f) {
+      const int64_t p0 = clause_ptr[clause_begin[f]], p1 = clause_ptr[clause_begin[f + 1]];
+      for (int64_t p = p0; p < p1; ++p) {
+        const int64_t v = lits[p] >> 1;
+        if (lits[p] < 0 || v < var_begin[f] || v >= var_begin[f + 1]) bad = 1;
+      }
+    }
+  }
+  const bool by_formula = F > 1 && !bad;
+  if (by_formula) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t f = 0; f < F; ++f) {
       const int64_t p0 = clause_ptr[clause_begin[f]], p1 = clause_ptr[clause_begin[f + 1]];
@@ -273,7 +287,7 @@ int gen_transpose(int32_t F, const int64_t* var_begin, const int64_t* clause_beg
   var_ptr[n] = (int32_t)acc;
   if (acc != L) return -1;
   std::vector<int32_t> fill(var_ptr, var_ptr + n);
-  if (F > 1) {
+  if (by_formula) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t f = 0; f < F; ++f) {
       const int64_t p0 = clause_ptr[clause_begin[f]], p1 = clause_ptr[clause_begin[f + 1]];
