@@ -172,6 +172,11 @@ void galsat_default_options(galsat_options* opt);
 
 /* Validates and copies the problem to the device, derives the occurrence
  * tables the kernels use, chooses a plan and allocates its workspace.
+ * The input is a CNF formula as the paper's SAT background subsection
+ * defines it (a conjunction of clauses, each a disjunction of literals) in
+ * both CSR orientations,
+ * and the restart count is the batch dimension B of Section 3.2 (independent
+ * random initialisations optimised together).
  * stream: used for the uploads (synchronised before returning).
  * On success *out holds a new handle; on failure *out is NULL and the
  * message is available from galsat_last_error(NULL). */
@@ -199,12 +204,17 @@ galsat_status galsat_init_state(galsat_handle h, float* x, int32_t ldx, uint64_t
 galsat_status galsat_loss_grad(galsat_handle h, const float* x, int32_t ldx, const float* upstream,
                                float* loss, float* grad, void* stream);
 
-/* `steps` iterations, each evaluated at the current x_k with every variable
- * updated from the same gradient (Jacobi):
+/* `steps` iterations of gradient descent on the relaxed loss (Section 3.2:
+ * clause value of Eq. (2) with the negation of Eq. (1), the clause-sum loss
+ * of Eq. (5) shifted by the clause count, and its gradient by
+ * backpropagation through the clause products).  Each iteration is
+ * evaluated at the current x_k with every variable updated from the same
+ * gradient (Jacobi):
  *   SGD_CLAMP  x_{k+1} = min(1, max(0, x_k - lr * g_k))
- *   ADAM       m, v moments and bias correction at the handle's step
- *              counter t (starting at 1, advanced once per step), then the
- *              same clamp.  opt_state: device FP32 [2][n][ldx] (m then v),
+ *   ADAM       the optimizer of the appendix "Experiment Setup" (there
+ *              with lr 0.5): m, v moments and bias correction at the
+ *              handle's step counter t (starting at 1, advanced once per
+ *              step), then the same clamp.  opt_state: device FP32 [2][n][ldx] (m then v),
  *              zero before the first step; NULL for SGD.
  * x is updated in place.  loss_trace ([steps][F*R] FP32) and unsat_trace
  * ([steps][F*R] int32), each optional, receive loss'(x_k) and the exact
@@ -288,10 +298,14 @@ galsat_status galsat_select_vars(galsat_handle h, const float* conf, int32_t num
                                  float frac, int32_t min_count, int32_t* offsets, int32_t* out,
                                  void* stream);
 
-/* Rounds x (x > 0.5 -> 1; an x that is already 0/1 is used as given),
- * counts unsatisfied clauses exactly per (formula, restart) with wavefront
- * ballot and popcount, and picks per formula the restart with the fewest
- * (ties to the lowest restart index): the hand-off of the GPU stage.
+/* Rounds x (x > 0.5 -> 1; an x that is already 0/1 is used as given; the
+ * argmax of Eq. (4) over the pair (1 - x, x) with a tie to 0), counts
+ * unsatisfied clauses exactly per (formula, restart) with wavefront ballot
+ * and popcount (a clause is unsatisfied when every literal is false, the
+ * 0/1 reading of Eq. (2)), and picks per formula the restart with the
+ * fewest (ties to the lowest restart index): the hand-off of the GPU stage
+ * to the CPU stage (architecture overview, Section 3.1, and Section 3.3:
+ * the batch of minimal clause loss is the one passed on).
  *   unsat        device int32 [F*R]
  *   best_restart device int32 [F] or NULL
  *   best_assign  device uint8 [n] or NULL: the rounded assignment of each

@@ -130,6 +130,14 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
   hipStream_t s = static_cast<hipStream_t>(stream);
   float* xs = nullptr;
   if (hipMalloc(&xs, (size_t)std::max(n, 1) * ldx * sizeof(float)) != hipSuccess) return GALSAT_ENOMEM;
+  // Adam candidates step their own moments [2][n][ldx], zeroed before each
+  const bool adam = base.optimizer == GALSAT_OPT_ADAM;
+  const size_t mom_bytes = 2 * (size_t)std::max(n, 1) * ldx * sizeof(float);
+  float* mom = nullptr;
+  if (adam && hipMalloc(&mom, mom_bytes) != hipSuccess) {
+    (void)hipFree(xs);
+    return GALSAT_ENOMEM;
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
@@ -159,9 +167,10 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
       break;
     }
     (void)hipMemcpyAsync(xs, x0, (size_t)n * ldx * sizeof(float), hipMemcpyDeviceToDevice, s);
-    st = galsat_step(h, xs, ldx, nullptr, 1, nullptr, nullptr, stream);  // warm-up
+    if (adam) (void)hipMemsetAsync(mom, 0, mom_bytes, s);
+    st = galsat_step(h, xs, ldx, mom, 1, nullptr, nullptr, stream);  // warm-up
     (void)hipEventRecord(e0, s);
-    if (st == GALSAT_OK) st = galsat_step(h, xs, ldx, nullptr, steps, nullptr, nullptr, stream);
+    if (st == GALSAT_OK) st = galsat_step(h, xs, ldx, mom, steps, nullptr, nullptr, stream);
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -179,6 +188,7 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(xs);
+  if (mom) (void)hipFree(mom);
   if (result != GALSAT_OK && best_plan.empty()) return result;
   if ((int32_t)best_plan.size() + 1 > plan_cap) return GALSAT_EINVAL;
   std::memcpy(plan_out, best_plan.c_str(), best_plan.size() + 1);

@@ -291,7 +291,12 @@ class Problem:
         ld = _state_ld(x, self.n, self.R)
         loss = torch.empty((self.F, self.R), dtype=torch.float32, device=x.device)
         if want_grad and grad is None:
-            grad = torch.empty_like(x)
+            # same strides as x (a column slice of a wider tensor keeps its
+            # row stride); columns past R are never written by the kernels,
+            # so they start at zero rather than uninitialised
+            grad = torch.empty_strided(x.size(), x.stride(), dtype=torch.float32, device=x.device)
+            if x.shape[1] > self.R:
+                grad[:, self.R:].zero_()
         if grad is not None:
             gl = _state_ld(grad, self.n, self.R, "grad")
             if gl != ld:

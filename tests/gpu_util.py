@@ -78,6 +78,23 @@ def check_update(x1_gpu: torch.Tensor, x1_ref: np.ndarray, x0: np.ndarray, R: in
     assert not bad.any(), f"update mismatch {what}: {bad.sum()} entries, worst {np.max(err / tol):.3g} x tol"
 
 
+def check_update_oracle(x1_gpu: torch.Tensor, x0: np.ndarray, g_ref: np.ndarray, A: np.ndarray,
+                        lr: float, R: int, what="", rows=None):
+    """x_{k+1} of the fused step against the oracle's projected SGD step from
+    the same x_k with the oracle's own gradient.  The gradient tolerance
+    carries through the step (the clamp is a contraction): |x1 - x1_ref| <=
+    lr * 1e-5 * (|g_ref| + A) + 1e-5 * |x1_ref - x0| + 2^-24."""
+    got = to_oracle(x1_gpu, R)
+    if rows is not None:
+        got = got[rows]
+    x1_ref = oracle.step_sgd(x0, g_ref, lr)
+    tol = lr * GRAD_RTOL * (np.abs(g_ref) + A) + LOSS_RTOL * np.abs(x1_ref - x0) + X_ULP
+    err = np.abs(got - x1_ref)
+    bad = err > tol
+    assert not bad.any(), (f"update mismatch {what}: {bad.sum()} of {bad.size}, worst "
+                           f"{np.max(err / tol):.3g} x tol")
+
+
 def check_counts(unsat_gpu: torch.Tensor, unsat_ref: np.ndarray, what=""):
     got = unsat_gpu.detach().cpu().numpy()
     assert np.array_equal(got, unsat_ref), f"unsat counts differ {what}: {(got != unsat_ref).sum()} entries"

@@ -575,6 +575,30 @@ def test_autograd_function():
     check_grad(x.grad, g_ref * w, A * np.abs(w), R, "autograd backward")
 
 
+def test_autograd_padded_and_sliced_state():
+    """The autograd backward on a state with padding columns (ld > R) and on
+    a column slice of a wider tensor: the gradient has x's strides, its
+    first R columns match the oracle and the padding columns are zero."""
+    say("[autograd] padded and sliced")
+    cnf = CASES["planted300"]()
+    R = 12
+    prob = Problem(cnf, R)
+    xr = np.random.default_rng(72).random((R, cnf.n))
+    lo_ref, g_ref, A = oracle.grad(cnf, xr, with_abs=True)
+    padded = from_oracle(xr, ld=16).requires_grad_(True)
+    wide = from_oracle(xr, ld=20)
+    sliced = wide[:, :R].detach().requires_grad_(True)
+    for name, x in (("padded", padded), ("sliced", sliced)):
+        loss = GalsatLoss.apply(x, prob)
+        loss.sum().backward()
+        torch.cuda.synchronize()
+        check_loss(loss.detach(), lo_ref, cnf, f"{name} forward")
+        check_grad(x.grad, g_ref, A, R, f"{name} backward")
+        assert x.grad.shape == x.shape
+        if x.shape[1] > R:
+            assert torch.count_nonzero(x.grad[:, R:]) == 0, "padding columns of grad"
+
+
 def test_round_check_ties_and_exact_points():
     say("[round]")
     cnf = CASES["mixed20k"]()
@@ -637,3 +661,16 @@ def test_autotune_and_plan_cache(tmp_path, monkeypatch):
     assert info["lanes_per_item"] == int(want["lpi"])
     assert info["restarts_per_lane"] == int(want["rpl"])
     parity_at(prob, cnf, x0, f"autotuned {plan}")
+
+
+def test_autotune_adam():
+    """The autotuner times Adam candidates with their own zeroed moments."""
+    say("[autotune] adam")
+    from paper_2603_28796_amd.galsat import autotune
+    cnf = CASES["planted300"]()
+    R = 16
+    x0 = _x0(cnf.n, R, 98)
+    plan, ms = autotune(cnf, R, x0, steps=2, optimizer="adam", lr=0.5)
+    assert ms > 0 and "lpi=" in plan
+    prob = Problem(cnf, R, optimizer="adam", lr=0.5, plan_override=plan)
+    parity_at(prob, cnf, x0, f"autotuned adam {plan}")

@@ -9,7 +9,8 @@ import torch
 import oracle
 from paper_2603_28796_amd import inputs as I
 from paper_2603_28796_amd.galsat import GalsatLoss, Problem
-from tests.gpu_util import (check_counts, check_grad, check_loss, from_oracle, say, to_oracle)
+from tests.gpu_util import (check_counts, check_grad, check_loss, check_update_oracle, from_oracle,
+                            say, to_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -91,6 +92,14 @@ def test_planted3sat_n1e5_autograd_and_fd():
         gs = to_oracle(xg.grad, R)[rows][:, vars_]
         tol = 1e-5 * (np.abs(fd) + A[:, vars_]) + 1e-9
         assert np.all(np.abs(gs - fd) <= tol), f"FD mismatch at step {k}"
+        if k in (0, 999):
+            # the fused update x_{k+1} of the benchmark's plan (eight
+            # XCD-pinned restart tiles, projected SGD epilogue) on a copy
+            assert prob.info()["lanes_per_item"] == 32 and prob.info()["restarts_per_lane"] == 4
+            x1 = x.clone()
+            prob.step(x1, 1)
+            check_update_oracle(x1, xs, g_ref, A, prob.lr, R, f"update at step {k}", rows=rows)
+            del x1
     unsat, best, assign = prob.round_check(x)
     torch.cuda.synchronize()
     say(f"  min unsat after 1000 steps: {int(unsat.min())}")
@@ -146,6 +155,8 @@ def test_batch4096_general_vs_plain_and_oracle():
     x = prob.init_state(I.SEED_BASE + 4)
     loss, g = prob.loss_grad(x)
     unsat, best, _ = prob.round_check(x, want_assign=False)
+    x1 = x.clone()
+    prob.step(x1, 1)
     torch.cuda.synchronize()
     fs = np.r_[0, 1, np.random.default_rng(3).choice(cnf.F, 14, replace=False), cnf.F - 1]
     for f in fs:
@@ -156,6 +167,8 @@ def test_batch4096_general_vs_plain_and_oracle():
         check_loss(loss[f:f + 1], lo_ref, sub, f"formula {f}")
         check_grad(g[v0:v1], g_ref, A, R, f"formula {f}")
         check_counts(unsat[f:f + 1], oracle.unsat(sub, xs), f"formula {f}")
+        check_update_oracle(x1[v0:v1], xs, g_ref, A, prob.lr, R, f"formula {f} update")
+    del x1
     say("  plain schedule")
     plain = Problem(cnf, R, lr=w.lr, schedule="plain")
     xa, xb = x.clone(), x.clone()
@@ -181,7 +194,16 @@ def test_large_n1e7_sampled():
     prob = Problem(cnf, R, lr=w.lr)
     say(f"  plan {prob.info()}")
     x = prob.init_state(I.SEED_BASE + 5)
-    sampled_parity(prob, cnf, x, np.array([0, 15]), "large step 0")
+    rows = np.array([0, 15])
+    sampled_parity(prob, cnf, x, rows, "large step 0")
+    # the fused update of the benchmark's plan on a copy of the state
+    x1 = x.clone()
+    prob.step(x1, 1)
+    torch.cuda.synchronize()
+    xs = to_oracle(x, R)[rows]
+    _, g_ref, A = oracle.grad(cnf, xs, with_abs=True)
+    check_update_oracle(x1, xs, g_ref, A, prob.lr, R, "large update at step 0", rows=rows)
+    del x1
     prob.step(x, 2)
     sampled_parity(prob, cnf, x, np.array([3]), "large step 2")
     xr = np.repeat(cnf.planted[None, :].astype(np.float64), R, axis=0)
