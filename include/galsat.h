@@ -313,6 +313,28 @@ galsat_status galsat_select_vars(galsat_handle h, const float* conf, int32_t num
 galsat_status galsat_round_check(galsat_handle h, const float* x, int32_t ldx, int32_t* unsat,
                                  int32_t* best_restart, uint8_t* best_assign, void* stream);
 
+/* Allocation-free variant of galsat_round_check, for callers that cannot
+ * allocate device memory during the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and kernels as galsat_round_check; its scratch (the rounding
+ * bit-planes, the per-chunk unsat rows, the finalize part sums and, when
+ * best_restart is NULL, the best restart) lives in a fixed 64 MiB device
+ * array of the library instead of the handle's workspace, so the call
+ * makes no hipMalloc, hipFree or other allocating call.  The array is
+ * per GPU and held until the process ends; its address is looked up once
+ * per device on the first call there.
+ *   Limit: 8*n*ceil(R/64) + 4*R*(clause chunks) + 786,432 + 4*F bytes
+ *   (each part rounded up to 256) must fit 64 MiB, else GALSAT_EOVERFLOW
+ *   with a message giving the size needed.
+ *   Must be called with the handle's device current (else GALSAT_EINVAL).
+ *   Every call on one GPU shares that GPU's array: calls that overlap in
+ *   time on one GPU (other streams, other threads, other handles) race and
+ *   must be serialised by the caller.  Nothing in the array needs to carry
+ *   over between calls (each call overwrites what it reads). */
+galsat_status galsat_round_check_static(galsat_handle h, const float* x, int32_t ldx,
+                                        int32_t* unsat, int32_t* best_restart,
+                                        uint8_t* best_assign, void* stream);
+
 /* Sets the Adam step counter (the next step uses t + 1); 0 restarts the bias
  * correction.  For checkpoint and resume. */
 galsat_status galsat_set_adam_step(galsat_handle h, int32_t t);

@@ -1989,6 +1989,85 @@ extern "C" galsat_status galsat_round_check(galsat_handle h, const float* x, int
   return GALSAT_OK;
 }
 
+// ------------------------------------------------ allocation-free round check
+//
+// The same kernels as galsat_round_check, with their scratch (bit-planes,
+// per-chunk unsat rows, split-finalize part sums, the best restart when the
+// caller does not ask for it) carved from one file-scope device array
+// instead of the handle's workspace.  The array's device address differs per
+// GPU and is looked up once per device with hipGetSymbolAddress; host code
+// uses only that looked-up address.
+namespace {
+
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;  // 64 MiB per device
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" galsat_status galsat_round_check_static(galsat_handle h, const float* x, int32_t ldx,
+                                                   int32_t* unsat, int32_t* best_restart,
+                                                   uint8_t* best_assign, void* stream) {
+  GS_CHECK_HANDLE(h);
+  if ((!x && h->n > 0) || !unsat) return h->fail(GALSAT_EINVAL, "x and unsat are required");
+  if (ldx < h->R) return h->fail(GALSAT_EINVAL, "ldx < restarts");
+  int dev = -1;
+  GS_HIP(h, hipGetDevice(&dev), "get device");
+  if (dev != h->device) return h->fail(GALSAT_EINVAL, "call on the device the handle was created on");
+  if (dev < 0 || dev >= kMaxDevices) return h->fail(GALSAT_EUNSUPPORTED, "device index above 63");
+  // the scratch layout for this handle; refused when it exceeds the array
+  const int64_t words = (h->R + 63) / 64;
+  const size_t b_bits = align256((size_t)h->n * (size_t)words * sizeof(uint64_t));
+  const size_t b_rows = align256((size_t)std::max(h->ach.count(), 1) * (size_t)h->R * sizeof(int32_t));
+  const size_t b_pl = align256((size_t)kFinalizeScratch * sizeof(double));
+  const size_t b_pu = align256((size_t)kFinalizeScratch * sizeof(int32_t));
+  const size_t b_best = align256((size_t)h->F * sizeof(int32_t));
+  const size_t need = b_bits + b_rows + b_pl + b_pu + b_best;
+  if (need > kStaticScratchBytes)
+    return h->fail(GALSAT_EOVERFLOW,
+                   "galsat_round_check_static needs " + std::to_string(need) +
+                       " bytes of scratch, above its fixed " +
+                       std::to_string(kStaticScratchBytes) + " (use galsat_round_check)");
+  // once per device, with that device current: the array's address on it
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? p : nullptr;
+  });
+  GS_HIP(h, g_scratch_err[dev], "scratch symbol address");
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  if (!base) return h->fail(GALSAT_EDEVICE, "scratch symbol address is null");
+  uint64_t* bits = reinterpret_cast<uint64_t*>(base);
+  int32_t* rows = reinterpret_cast<int32_t*>(base + b_bits);
+  double* part_l = reinterpret_cast<double*>(base + b_bits + b_rows);
+  int32_t* part_u = reinterpret_cast<int32_t*>(base + b_bits + b_rows + b_pl);
+  int32_t* best_tmp = reinterpret_cast<int32_t*>(base + b_bits + b_rows + b_pl + b_pu);
+  // every kernel below overwrites the scratch entries it later reads, so
+  // nothing needs clearing between calls; no per-kernel profiling events
+  // either (creating one may allocate)
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GS_HIP(h, launch_pack_bits(x, ldx, h->n, h->R, bits, s), "pack bits");
+  GS_HIP(h, launch_count_unsat(h->clause_ptr, h->clause_lits, h->ach_beg, h->ach_end, h->ach.count(),
+                               bits, h->n, h->R, rows, s),
+         "count unsat");
+  FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->zero_empty, nullptr, rows,
+                  nullptr, unsat, h->R, 0, part_l, part_u, 1, h->max_all_rows};
+  GS_HIP(h, launch_finalize(fa, h->F, s), "finalize");
+  if (best_restart || best_assign) {
+    int32_t* best = best_restart ? best_restart : best_tmp;
+    GS_HIP(h, launch_best(unsat, h->F, h->R, best, s), "best");
+    if (best_assign)
+      GS_HIP(h, launch_best_assign(bits, h->n, h->var_formula, best, best_assign, s), "best assign");
+  }
+  return GALSAT_OK;
+}
+
 extern "C" galsat_status galsat_profile(galsat_handle h, int32_t enable) {
   GS_CHECK_HANDLE(h);
   if (enable) {

@@ -79,7 +79,7 @@ class _Info(ctypes.Structure):
 EXPORTS = ("galsat_default_options", "galsat_create", "galsat_destroy", "galsat_init_state",
            "galsat_loss_grad", "galsat_step", "galsat_step_prepare", "galsat_gumbel_step",
            "galsat_gumbel_noise", "galsat_candidates", "galsat_confidence",
-           "galsat_select_vars", "galsat_round_check",
+           "galsat_select_vars", "galsat_round_check", "galsat_round_check_static",
            "galsat_set_adam_step",
            "galsat_autotune", "galsat_get_info", "galsat_profile", "galsat_kernel_times",
            "galsat_tseitin",
@@ -129,6 +129,7 @@ def load_library(path: Optional[str] = None):
     lib.galsat_confidence.argtypes = [_P, _P, _I32, _P, ctypes.c_float, _P, _P]
     lib.galsat_select_vars.argtypes = [_P, _P, _I32, _I32, ctypes.c_float, _I32, _P, _P, _P]
     lib.galsat_round_check.argtypes = [_P, _P, _I32, _P, _P, _P, _P]
+    lib.galsat_round_check_static.argtypes = [_P, _P, _I32, _P, _P, _P, _P]
     lib.galsat_set_adam_step.argtypes = [_P, _I32]
     lib.galsat_get_info.argtypes = [_P, ctypes.POINTER(_Info)]
     lib.galsat_profile.argtypes = [_P, _I32]
@@ -418,6 +419,22 @@ class Problem:
         self._check(self._lib.galsat_round_check(self._h, _ptr(x), ld, _ptr(unsat), _ptr(best),
                                                  _ptr(assign), _stream()), "galsat_round_check")
         return unsat, best, assign
+
+    def round_check_static(self, x: torch.Tensor, unsat: torch.Tensor, best: Optional[torch.Tensor] = None,
+                           assign: Optional[torch.Tensor] = None):
+        """galsat_round_check_static into caller-provided buffers (unsat [F, R]
+        int32, best [F] int32 or None, assign [n] uint8 or None): the library
+        allocates nothing during the call."""
+        ld = _state_ld(x, self.n, self.R)
+        if unsat.dtype != torch.int32 or unsat.numel() != self.F * self.R or not unsat.is_contiguous():
+            raise ValueError("unsat must be a contiguous int32 tensor of F*R elements")
+        if best is not None and (best.dtype != torch.int32 or best.numel() != self.F):
+            raise ValueError("best must be an int32 tensor of F elements")
+        if assign is not None and (assign.dtype != torch.uint8 or assign.numel() != self.n):
+            raise ValueError("assign must be a uint8 tensor of n elements")
+        self._check(self._lib.galsat_round_check_static(self._h, _ptr(x), ld, _ptr(unsat), _ptr(best),
+                                                        _ptr(assign), _stream()),
+                    "galsat_round_check_static")
 
     def set_adam_step(self, t: int):
         self._check(self._lib.galsat_set_adam_step(self._h, int(t)), "galsat_set_adam_step")
