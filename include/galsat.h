@@ -109,12 +109,17 @@ enum { GALSAT_OPT_SGD_CLAMP = 0, GALSAT_OPT_ADAM = 1 };
  *              them in var_occ order.
  *   RECOMPUTE  the variable-parallel side recomputes them from x, so no
  *              per-literal or per-clause values are kept between passes.
- *   AUTO       the plan's choice, within workspace_budget_bytes: with the
- *              single-pass gradient (more than 32 restarts), clauses up to
+ *   AUTO       the plan's choice, within workspace_budget_bytes: with at
+ *              most 64 restarts the flat gradient (3-literal clauses
+ *              recompute from x; every other clause is reduced once per
+ *              step to a per-clause row holding the product of its nonzero
+ *              factors and its count of zero factors, from which each
+ *              occurrence's partial follows by one division); with more
+ *              restarts the single-pass gradient, where clauses up to
  *              recompute_max_len literals (default 8) recompute and longer
- *              ones store; with the two-phase gradient (at most 32
- *              restarts), every clause stores, unless recompute_max_len is
- *              set. */
+ *              ones store; with an explicit two-phase gradient (plan key
+ *              two=1), every clause stores, unless recompute_max_len is set.
+ *              Sums run in a fixed order in every plan. */
 enum { GALSAT_PARTIALS_AUTO = 0, GALSAT_PARTIALS_STORE = 1, GALSAT_PARTIALS_RECOMPUTE = 2 };
 
 /* Execution schedule of galsat_step:
@@ -163,7 +168,9 @@ typedef struct {
                               formulas in index order, not LPT order), xpin (1: the
                               single pass maps restart tiles to XCDs by linear block
                               id, 0: off; on by default for one formula with at least
-                              1,024 restarts).  Keys left out take the plan's own
+                              1,024 restarts), flat (1: the flat gradient, 0: not; on by
+                              default for at most 64 restarts with AUTO partials and no
+                              two= or krec= key).  Keys left out take the plan's own
                               choice. */
 } galsat_options;
 
@@ -373,6 +380,9 @@ typedef struct {
   int32_t adam_step;
   int32_t lds_restarts_per_group; /* LDS schedule: restarts per workgroup, 0: not used */
   int32_t lds_staged;           /* LDS schedule: 1 when the records are copied to LDS */
+  int32_t flat;                 /* 1: flat gradient (3-literal clauses recomputed from pair
+                                   records, every other clause through a per-clause row) */
+  int32_t clause_rows;          /* flat gradient: clauses reduced to a per-clause row */
 } galsat_info;
 
 galsat_status galsat_get_info(galsat_handle h, galsat_info* info);
@@ -386,7 +396,8 @@ galsat_status galsat_get_info(galsat_handle h, galsat_info* info);
  * their summed duration in milliseconds. */
 enum {
   GALSAT_K_VAR_PASS = 0,     /* variable-parallel gather + fused update / gradient */
-  GALSAT_K_CLAUSE_PASS = 1,  /* clause-parallel forward and stored partials */
+  GALSAT_K_CLAUSE_PASS = 1,  /* clause-parallel forward and stored partials (flat plan: the
+                                clause-row pass) */
   GALSAT_K_FINALIZE = 2,     /* fixed-order reduction of per-chunk partial sums */
   GALSAT_K_COPY = 3,         /* state copy between the caller's and internal layouts */
   GALSAT_K_PACK = 4,         /* rounding bit-pack (ballot) */
@@ -394,7 +405,9 @@ enum {
   GALSAT_K_SELECT = 6,       /* best restart and its assignment */
   GALSAT_K_OCC_PASS = 7,     /* two-phase plan: occurrence-parallel contributions */
   GALSAT_K_VAR_SUM = 8,      /* two-phase plan: per-variable sums + fused update */
-  GALSAT_K_KINDS = 9
+  GALSAT_K_SEG_PASS = 9,     /* partial gradients of the segments of split variables */
+  GALSAT_K_HEAVY = 10,       /* split variables: fixed-order sum of their segments + update */
+  GALSAT_K_KINDS = 11
 };
 
 typedef struct {

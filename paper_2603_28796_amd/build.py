@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgalsat.so")
-SOURCES = ["galsat_varpass.hip", "galsat_twophase.hip", "galsat_clause.hip", "galsat_modes.hip",
+SOURCES = ["galsat_varpass.hip", "galsat_flat.hip", "galsat_twophase.hip", "galsat_clause.hip", "galsat_modes.hip",
            "galsat_persist.hip",
            "galsat_host.hip", "galsat_tseitin.hip", "galsat_tune.hip"]
 

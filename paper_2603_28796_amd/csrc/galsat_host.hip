@@ -137,6 +137,7 @@ struct galsat_ctx {
   int stream_items = 0;  // streaming variable pass
   int xcd_pin = 0;       // single pass: restart tiles mapped to XCDs
   int two_phase = 0;     // occurrence pass + variable sum instead of the single pass
+  int flat = 0;          // flat plan: pair records + clause rows (galsat_flat.hip)
   int32_t xseq = 0;      // chunks of the XCD-contiguous order (0: off)
   int lds_rg = 0;        // restart group of the persistent LDS schedule (0: not used)
   int lds_stage = 0;     // its occurrence records staged in LDS
@@ -152,6 +153,7 @@ struct galsat_ctx {
   Chunks vch, sch, ach;  // var chunks, stored-clause chunks, all-clause chunks
   Chunks segch;          // chunks of segments of split variables
   Chunks och;            // occurrence-range chunks of the two-phase plan
+  Chunks rch;            // chunks of the flat plan's clause-row list
   std::vector<int32_t> heavy_f_first;  // [F+1] split variables of each formula
   int32_t n_heavy = 0, n_seg = 0, step_rows = 0;
 
@@ -181,6 +183,15 @@ struct galsat_ctx {
   std::vector<ClauseClass> cls;
   int32_t *segch_beg = nullptr, *segch_end = nullptr, *segch_row = nullptr;
   int32_t *ach_beg = nullptr, *ach_end = nullptr;
+  // flat plan
+  int2* pairs = nullptr;
+  int32_t *pair_first = nullptr, *pair_mid = nullptr, *lrec_ptr = nullptr;
+  uint32_t* lrec = nullptr;
+  uint32_t* qrow = nullptr;  // [clause rows][ld] packed per-clause products
+  int32_t *row_ids = nullptr, *rch_beg = nullptr, *rch_end = nullptr, *rch_row = nullptr;
+  int32_t* rch_order = nullptr;
+  int32_t n_rorder = 0;
+  int32_t* vch_fvb = nullptr;  // [variable chunks] first variable of the chunk's formula
   int32_t *seg_var = nullptr, *seg_q0 = nullptr, *seg_q1 = nullptr;
   int32_t *heavy_var = nullptr, *heavy_sbeg = nullptr;
   int32_t *fin_step_a0 = nullptr, *fin_step_a1 = nullptr;
@@ -384,12 +395,13 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // (one formula: about this many chunks in an XCD-contiguous order), segdiv,
 // ldsrg (restarts per workgroup of the LDS schedule: 1, 2, 4, 8, 16 or 32)
 // ldsstage (0: the LDS schedule reads records from global memory), ldslpt
-// (0: the LDS schedule issues formulas in index order) and xpin (1/0: the
-// single pass maps restart tiles to XCDs or not).
+// (0: the LDS schedule issues formulas in index order), xpin (1/0: the
+// single pass maps restart tiles to XCDs or not) and flat (1/0: the flat
+// plan of pair records and clause rows, or not).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
                     int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
                     int* short_clauses, int* xseq, int* segdiv, int* ldsrg, int* ldsstage,
-                    int* ldslpt, int* xpin) {
+                    int* ldslpt, int* xpin, int* flat) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -418,6 +430,7 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "ldsstage") *ldsstage = v;
       else if (k == "ldslpt") *ldslpt = v;
       else if (k == "xpin") *xpin = v;
+      else if (k == "flat") *flat = v;
     }
     pos = comma + 1;
   }
@@ -600,10 +613,10 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // ---- plan: which clauses recompute their partials in the variable pass
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
   int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1, segdiv_o = -1;
-  int ldsrg_o = 0, ldsstage_o = -1, ldslpt_o = -1, xpin_o = -1;
+  int ldsrg_o = 0, ldsstage_o = -1, ldslpt_o = -1, xpin_o = -1, flat_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
                  &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o, &ldsrg_o, &ldsstage_o,
-                 &ldslpt_o, &xpin_o);
+                 &ldslpt_o, &xpin_o, &flat_o);
   const bool csort = csort_o != 0;
   // Persistent LDS schedule: every formula's restart group must fit in LDS
   // (state double-buffered); SGD only; every clause recomputed.
@@ -673,12 +686,34 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       (size_t)L * (size_t)h->ldD * sizeof(float) > opt.workspace_budget_bytes)
     h->two_phase = 0;
   if (h->stream_items || lds_rg) h->two_phase = 0;
+  // Flat plan (galsat_flat.hip): 3-literal clauses recomputed from pair
+  // records, every other clause reduced once per step to a row of packed
+  // per-clause products.  By default for narrow restart batches (at most 64)
+  // with AUTO partials and no explicit gradient-plan override; it needs
+  // formula-local literal codes below 2^31 and the clause rows within the
+  // workspace budget.
+  {
+    const bool krec_set = opt.recompute_max_len > 0 ||
+                          (opt.plan_override && std::strstr(opt.plan_override, "krec="));
+    bool fit = !h->stream_items && !lds_rg && opt.partials != GALSAT_PARTIALS_RECOMPUTE;
+    for (int32_t f = 0; f < F && fit; ++f) fit = fvb[f + 1] - fvb[f] < (1 << 30);
+    if (fit && opt.workspace_budget_bytes > 0) {
+      int64_t rows = 0;
+      for (int32_t t = 0; t < m; ++t) rows += (cp[t + 1] - cp[t] != 3 && cp[t + 1] > cp[t]) ? 1 : 0;
+      fit = (size_t)rows * (size_t)round_up(R, 4) * sizeof(uint32_t) <= opt.workspace_budget_bytes;
+    }
+    const bool auto_flat = flat_o < 0 && two_o < 0 && !krec_set && R <= 64 &&
+                           opt.partials == GALSAT_PARTIALS_AUTO;
+    h->flat = fit && (flat_o > 0 || auto_flat) ? 1 : 0;
+    if (h->flat) h->two_phase = 0;
+  }
   // chunks per formula of the XCD-aware order (several formulas per launch)
   const int64_t xcd_chunks =
       xcdc_o >= 0 ? xcdc_o : (h->two_phase ? kXcdChunksTwoPhase : kXcdChunks);
   h->tile = choose_tile(R, 4);
-  if (h->two_phase && R % 4 == 0 && R >= 16) {
-    // four restarts per lane measured faster for the two-phase passes
+  if ((h->two_phase || h->flat) && R % 4 == 0 && R >= 16) {
+    // four restarts per lane measured faster for the two-phase passes (and
+    // the flat plan, whose per-record decoding then serves four restarts)
     h->tile.rpl = 4;
     h->tile.lpi = std::max(4, std::min(64, pow2_ceil(R / 4)));
   }
@@ -688,7 +723,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // XCD's L2 holds one tile's lines.  Measured 7 % faster per step than
   // 256-restart tiles two per launch at R = 1024.
   bool xpin_auto = false;
-  if (xpin_o < 0 && !h->two_phase && !h->stream_items && !lds_rg && F == 1 && R >= 1024 &&
+  if (xpin_o < 0 && !h->two_phase && !h->flat && !h->stream_items && !lds_rg && F == 1 && R >= 1024 &&
       R % 256 == 0 && opt.schedule != GALSAT_SCHED_PLAIN) {
     xpin_auto = true;
     h->xcd_pin = 1;
@@ -738,6 +773,12 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     krec = kmax;  // recompute everything: no per-literal storage at all
     stored = 0;
   }
+  if (h->flat) {
+    // the flat plan keeps no per-literal rows: its clause rows are planned
+    // below, and no old-style occurrence record is built
+    krec = kmax;
+    stored = 0;
+  }
   h->krec = krec;
   h->stored = stored;
 
@@ -747,8 +788,9 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // id and position.  Stored rows are numbered in variable-major order so a
   // variable's stored partials are contiguous.
   // filled completely below, so left uninitialised
-  std::unique_ptr<int4[]> occ4(new int4[(size_t)L + 1]);
-  const bool need_x = krec >= 5 && kmax >= 5;  // some inline record holds 4 to 7 others
+  const bool flat = h->flat != 0;
+  std::unique_ptr<int4[]> occ4(new int4[flat ? 1 : (size_t)L + 1]);
+  const bool need_x = !flat && krec >= 5 && kmax >= 5;  // some inline record holds 4 to 7 others
   std::unique_ptr<int4[]> occx(new int4[need_x ? (size_t)L + 1 : 1]);
   std::unique_ptr<int32_t[]> occ_cost(new int32_t[(size_t)L + 1]);
   std::unique_ptr<int32_t[]> lit_dslot(new int32_t[stored > 0 ? (size_t)L + 1 : 1]);
@@ -772,6 +814,12 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       int64_t d = sbase[v];
       for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
         const int32_t p = vo[q], t = clause_of[p], k = cp[t + 1] - cp[t];
+        if (flat) {
+          // gathers per restart: two other rows (3-literal clause) or one
+          // clause row
+          occ_cost[q] = k == 3 ? 2 : 1;
+          continue;
+        }
         const int32_t sign_first = ((cl[p] & 1) << 3) | ((p == cp[t]) ? 16 : 0);
         if (k > krec) {
           // two-phase: the clause pass writes the contribution straight into
@@ -799,6 +847,83 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     });
   }
   ptimer.mark("records");
+  // ---- flat plan tables.  Clause rows: every clause that is not 3
+  // literals long (and not empty), per formula longest first.  Per
+  // variable, in variable-major slot order: pair records of the 3-literal
+  // clauses whose first literal is the variable's own occurrence, then the
+  // other pair records, then clause-row records.
+  std::vector<int32_t> row_ids, row_of, pair_first, pair_mid, lrec_ptr;
+  std::vector<int64_t> f_rbeg((size_t)F + 1, 0);
+  std::vector<int2> pairs;
+  std::vector<uint32_t> lrec;
+  if (flat) {
+    row_of.assign((size_t)std::max(m, 1), -1);
+    for (int32_t f = 0; f < F; ++f) {
+      f_rbeg[f] = (int64_t)row_ids.size();
+      for (int32_t t = fcb[f]; t < fcb[f + 1]; ++t) {
+        const int32_t k = cp[t + 1] - cp[t];
+        if (k != 3 && k > 0) row_ids.push_back(t);
+      }
+      std::stable_sort(row_ids.begin() + f_rbeg[f], row_ids.end(), [&](int32_t a2, int32_t b2) {
+        return cp[a2 + 1] - cp[a2] > cp[b2 + 1] - cp[b2];
+      });
+    }
+    f_rbeg[F] = (int64_t)row_ids.size();
+    for (size_t i = 0; i < row_ids.size(); ++i) row_of[row_ids[i]] = (int32_t)i;
+    std::vector<int64_t> np((size_t)n + 1, 0), nr((size_t)n + 1, 0), nf((size_t)n, 0);
+    parallel_for(n, [&](int64_t v0, int64_t v1) {
+      for (int64_t v = v0; v < v1; ++v) {
+        int64_t a3 = 0, fst = 0, b = 0;
+        for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
+          const int32_t p = vo[q], t = clause_of[p];
+          if (cp[t + 1] - cp[t] == 3) {
+            ++a3;
+            fst += p == cp[t] ? 1 : 0;
+          } else {
+            ++b;
+          }
+        }
+        np[v + 1] = a3;
+        nr[v + 1] = b;
+        nf[v] = fst;
+      }
+    });
+    for (int32_t v = 0; v < n; ++v) {
+      np[v + 1] += np[v];
+      nr[v + 1] += nr[v];
+    }
+    pair_first.resize((size_t)n + 1);
+    pair_mid.resize((size_t)std::max(n, 1));
+    lrec_ptr.resize((size_t)n + 1);
+    for (int32_t v = 0; v <= n; ++v) {
+      pair_first[v] = (int32_t)np[v];
+      lrec_ptr[v] = (int32_t)nr[v];
+      if (v < n) pair_mid[v] = (int32_t)(np[v] + nf[v]);
+    }
+    pairs.resize((size_t)std::max<int64_t>(np[n], 1));
+    lrec.resize((size_t)std::max<int64_t>(nr[n], 1));
+    parallel_for(n, [&](int64_t v0, int64_t v1) {
+      for (int64_t vv = v0; vv < v1; ++vv) {
+        const int32_t v = (int32_t)vv;
+        const int32_t base2 = 2 * fvb[var_formula[v]];
+        int64_t af = pair_first[v], ao = pair_mid[v], b = lrec_ptr[v];
+        for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
+          const int32_t p = vo[q], t = clause_of[p];
+          const uint32_t own_neg = (uint32_t)(cl[p] & 1) << 31;
+          if (cp[t + 1] - cp[t] == 3) {
+            int32_t o[2], c = 0;
+            for (int32_t i = cp[t]; i < cp[t + 1]; ++i)
+              if (i != p) o[c++] = cl[i] - base2;
+            const int2 rec = make_int2((int32_t)((uint32_t)o[0] | own_neg), o[1]);
+            if (p == cp[t]) pairs[(size_t)af++] = rec;
+            else pairs[(size_t)ao++] = rec;
+          } else {
+            lrec[(size_t)b++] = (uint32_t)row_of[t] | own_neg;
+          }
+        }
+      }
+    });
+  }
   std::vector<int32_t> stored_ids;
   std::vector<int64_t> f_sbeg((size_t)F + 1, 0);
   for (int32_t f = 0; f < F; ++f) {
@@ -1126,6 +1251,26 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
                                  per_formula_targets(cls_fbeg[c], pre));
     }
   }
+  // flat plan: chunks of the clause-row list, in the same formula groups
+  // of the XCD-aware order as the variable chunks
+  std::vector<int32_t> rorder;
+  if (flat) {
+    std::vector<int64_t> pre(row_ids.size() + 1, 0);
+    for (size_t i = 0; i < row_ids.size(); ++i)
+      pre[i + 1] = pre[i] + 1 + (cp[row_ids[i] + 1] - cp[row_ids[i]]);
+    if (xcd_all) {
+      std::vector<int64_t> ft((size_t)F);
+      for (int32_t f = 0; f < F; ++f)
+        ft[f] = std::max<int64_t>(64, (pre[f_rbeg[f + 1]] - pre[f_rbeg[f]]) / xcd_chunks);
+      h->rch = make_chunks(F, f_rbeg, pre, 0, &ft);
+      xcd_order_all(h->rch, &rorder);
+    } else {
+      h->rch = make_chunks(F, f_rbeg, pre, std::max<int64_t>(64, pre.back() / chunks_target),
+                           per_formula_targets(f_rbeg, pre));
+    }
+  } else {
+    h->rch.f_first.assign((size_t)F + 1, 0);
+  }
   {
     std::vector<int64_t> pre((size_t)m + 1, 0), fb(fcb.begin(), fcb.end());
     for (int32_t t = 0; t < m; ++t) pre[t + 1] = pre[t] + 1 + (cp[t + 1] - cp[t]);
@@ -1141,9 +1286,9 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // (two-phase: its occurrence chunks, then its stored-clause chunks; the
   // variable sums write no partial rows)
   const int VC = h->vch.count(), SC = h->sch.count(), GC = h->segch.count(), AC = h->ach.count();
-  const int OC = h->och.count();
-  std::vector<int32_t> vrow(VC, 0), srow(SC), grow(GC, 0), orow(OC), frow0(F), frow1(F), faa0(F),
-      faa1(F);
+  const int OC = h->och.count(), RC = h->rch.count();
+  std::vector<int32_t> vrow(VC, 0), srow(SC), grow(GC, 0), orow(OC), rrow(RC), frow0(F), frow1(F),
+      faa0(F), faa1(F);
   std::vector<std::vector<int32_t>> crow((size_t)NCL);
   for (int c = 0; c < NCL; ++c) crow[c].assign((size_t)h->cls[c].ch.count(), 0);
   auto class_rows = [&](int32_t f, int32_t* row) {
@@ -1164,6 +1309,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
         continue;
       }
       for (int c = h->vch.f_first[f]; c < h->vch.f_first[f + 1]; ++c) vrow[c] = row++;
+      for (int c = h->rch.f_first[f]; c < h->rch.f_first[f + 1]; ++c) rrow[c] = row++;
       for (int c = h->sch.f_first[f]; c < h->sch.f_first[f + 1]; ++c) srow[c] = row++;
       class_rows(f, &row);
       for (int c = h->segch.f_first[f]; c < h->segch.f_first[f + 1]; ++c) grow[c] = row++;
@@ -1208,7 +1354,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UPP(clause_lits, cl, L);
   UPP(var_ptr, vp, n + 1);
 #undef UPP
-  if ((he = c->upload(&c->occ4, occ4.get(), (size_t)L, s)) != hipSuccess ||
+  // (the flat plan builds no old-style records: one placeholder entry)
+  if ((he = c->upload(&c->occ4, occ4.get(), flat ? (size_t)1 : (size_t)L, s)) != hipSuccess ||
       (need_x && (he = c->upload(&c->occx, occx.get(), (size_t)L, s)) != hipSuccess))
     return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
                        std::string("upload occurrence records: ") + hipGetErrorString(he));
@@ -1279,6 +1426,24 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
         (he = c->upload(&cc.row, crow[k].data(), crow[k].size(), s)) != hipSuccess)
       return create_fail(he == hipErrorOutOfMemory ? GALSAT_ENOMEM : GALSAT_EDEVICE,
                          std::string("upload clause classes: ") + hipGetErrorString(he));
+  }
+  if (flat) {
+    UP(pairs, pairs);
+    UP(pair_first, pair_first);
+    UP(pair_mid, pair_mid);
+    UP(lrec, lrec);
+    UP(lrec_ptr, lrec_ptr);
+    UP(row_ids, row_ids);
+    UP(rch_beg, c->rch.beg);
+    UP(rch_end, c->rch.end);
+    UP(rch_row, rrow);
+    UP(rch_order, rorder);
+    c->n_rorder = (int32_t)rorder.size();
+    std::vector<int32_t> vfvb((size_t)std::max(VC, 1), 0);
+    for (int32_t f = 0; f < F; ++f)
+      for (int ch = c->vch.f_first[f]; ch < c->vch.f_first[f + 1]; ++ch) vfvb[ch] = fvb[f];
+    UP(vch_fvb, vfvb);
+    AL(qrow, (size_t)std::max<size_t>(row_ids.size(), 1) * (size_t)c->ld);
   }
   UP(segch_beg, c->segch.beg);
   UP(segch_end, c->segch.end);
@@ -1374,6 +1539,9 @@ extern "C" galsat_status galsat_get_info(galsat_handle h, galsat_info* info) {
   info->adam_step = h->adam_t;
   info->lds_restarts_per_group = h->lds_rg;
   info->lds_staged = h->lds_stage;
+  info->flat = h->flat;
+  info->clause_rows = h->flat ? (int32_t)(h->rch.count() > 0 ? h->rch.end.back() : 0) : 0;
+  if (h->flat) info->clause_chunks = h->rch.count();
   return GALSAT_OK;
 }
 
@@ -1426,6 +1594,15 @@ VarPassArgs var_args(const galsat_ctx* h) {
   a.C = h->D;
   a.D = h->D;
   a.ldD = h->ldD;
+  a.pairs = h->pairs;
+  a.pair_first = h->pair_first;
+  a.pair_mid = h->pair_mid;
+  a.lrec = h->lrec;
+  a.lrec_ptr = h->lrec_ptr;
+  a.qrow = h->qrow;
+  a.ldq = h->ld;
+  a.chunk_fvb = h->vch_fvb;
+  a.f_vbeg = h->f_vbeg;
   a.loss_part = h->loss_part;
   a.unsat_part = h->unsat_part;
   a.R = h->R;
@@ -1482,10 +1659,80 @@ galsat_status two_phase_passes(galsat_ctx* h, VarPassArgs va, Tile t, int mode, 
     ga.chunk_base = gc0;
     ga.chunk_order = nullptr;
     {
-      ProfScope _ps(h, GALSAT_K_VAR_SUM, s);
+      ProfScope _ps(h, GALSAT_K_SEG_PASS, s);
       GS_HIP(h, launch_seg_sum(ga, t, gc1 - gc0, s), "segment sum");
     }
-    ProfScope _ps(h, GALSAT_K_VAR_SUM, s);
+    ProfScope _ps(h, GALSAT_K_HEAVY, s);
+    GS_HIP(h, launch_heavy_finish(va, mode, t, h->heavy_f_first[f0], h->heavy_f_first[f1], s),
+           "split-variable finish");
+  }
+  return GALSAT_OK;
+}
+
+// The flat plan's gradient of one restart-tile group: the clause rows of
+// every clause that is not 3 literals long, then the whole variables (pair
+// records and clause rows) with the epilogue, then the split variables'
+// segments and their finish.
+galsat_status flat_passes(galsat_ctx* h, VarPassArgs va, Tile t, int mode, int f0, int f1,
+                          hipStream_t s) {
+  const bool all = f0 == 0 && f1 == h->F;
+  const int rc0 = h->rch.f_first[f0], rc1 = h->rch.f_first[f1];
+  if (rc1 > rc0) {
+    ClausePassArgs ca{};
+    ca.clause_ptr = h->clause_ptr;
+    ca.clause_lits = h->clause_lits;
+    ca.clause_ids = h->row_ids;
+    ca.chunk_cbeg = h->rch_beg;
+    ca.chunk_cend = h->rch_end;
+    ca.chunk_row = h->rch_row;
+    ca.chunk_base = rc0;
+    int blocks = rc1 - rc0;
+    if (h->n_rorder > 0 && all) {
+      ca.chunk_order = h->rch_order;
+      ca.chunk_base = 0;
+      blocks = h->n_rorder;
+    }
+    ca.tile_base = va.tile_base;
+    ca.tile_count = va.tile_count;
+    ca.x = va.x;
+    ca.ldx = va.ldx;
+    ca.loss_part = h->loss_part;
+    ca.unsat_part = h->unsat_part;
+    ca.R = h->R;
+    ca.qrow = h->qrow;
+    ca.ldq = h->ld;
+    ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
+    GS_HIP(h, launch_row_clause(ca, t, blocks, s), "clause-row pass");
+  }
+  {
+    VarPassArgs a = va;
+    a.chunk_vbeg = h->vch_beg;
+    a.chunk_vend = h->vch_end;
+    a.chunk_row = h->vch_row;
+    a.chunk_base = h->vch.f_first[f0];
+    int blocks = h->vch.f_first[f1] - h->vch.f_first[f0];
+    a.chunk_order = nullptr;
+    if (h->n_vorder > 0 && all) {
+      a.chunk_order = h->vch_order;
+      a.chunk_base = 0;
+      blocks = h->n_vorder;
+    }
+    ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+    GS_HIP(h, launch_flat_var(a, mode, t, blocks, s), "flat variable pass");
+  }
+  const int gc0 = h->segch.f_first[f0], gc1 = h->segch.f_first[f1];
+  if (gc1 > gc0) {
+    VarPassArgs ga = va;
+    ga.chunk_vbeg = h->segch_beg;
+    ga.chunk_vend = h->segch_end;
+    ga.chunk_row = h->segch_row;
+    ga.chunk_base = gc0;
+    ga.chunk_order = nullptr;
+    {
+      ProfScope _ps(h, GALSAT_K_SEG_PASS, s);
+      GS_HIP(h, launch_flat_seg(ga, t, gc1 - gc0, s), "flat segment pass");
+    }
+    ProfScope _ps(h, GALSAT_K_HEAVY, s);
     GS_HIP(h, launch_heavy_finish(va, mode, t, h->heavy_f_first[f0], h->heavy_f_first[f1], s),
            "split-variable finish");
   }
@@ -1586,6 +1833,11 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
     }
     va.tile_base = tb;
     va.tile_count = tc;
+    if (h->flat) {
+      st = flat_passes(h, va, t, mode, f0, f1, s);
+      if (st != GALSAT_OK) return st;
+      continue;
+    }
     if (h->two_phase) {
       st = two_phase_passes(h, va, t, mode, f0, f1, s);
       if (st != GALSAT_OK) return st;
@@ -1614,10 +1866,10 @@ galsat_status grad_passes(galsat_ctx* h, Tile t, int mode, const float* x, int32
       sa.chunk_row = h->segch_row;
       sa.chunk_base = gc0;
       {
-        ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+        ProfScope _ps(h, GALSAT_K_SEG_PASS, s);
         GS_HIP(h, launch_var_seg(sa, t, gc1 - gc0, s), "segment pass");
       }
-      ProfScope _ps(h, GALSAT_K_VAR_PASS, s);
+      ProfScope _ps(h, GALSAT_K_HEAVY, s);
       GS_HIP(h, launch_heavy_finish(va, mode, t, h->heavy_f_first[f0], h->heavy_f_first[f1], s),
              "split-variable finish");
     }

@@ -66,6 +66,17 @@ struct VarPassArgs {
   float lr;
   float b1, b2, eps;
   double inv_c1, inv_c2;        // Adam bias corrections 1/(1-b^t)
+  // flat plan (galsat_flat.hip)
+  const int2* pairs;            // [pairs] {other code 1 | own_neg << 31, other code 2}, codes
+                                // relative to the first variable of the formula
+  const int32_t* pair_first;    // [n+1] first pair of each variable (first-literal pairs first)
+  const int32_t* pair_mid;      // [n] first pair of each variable whose own literal is not first
+  const uint32_t* lrec;         // [row records] clause row | own_neg << 31
+  const int32_t* lrec_ptr;      // [n+1]
+  const uint32_t* qrow;         // [clause rows][ldq] packed per-clause products
+  int64_t ldq;
+  const int32_t* chunk_fvb;     // [chunks] first variable of each variable chunk's formula
+  const int32_t* f_vbeg;        // [F+1]
 };
 
 // Arguments of the clause-parallel pass (forward, and prefix/suffix
@@ -91,6 +102,8 @@ struct ClausePassArgs {
   double* loss_part;
   int32_t* unsat_part;
   int32_t R;
+  uint32_t* qrow;               // row pass of the flat plan: [list][ldq] packed clause values
+  int64_t ldq;
 };
 
 struct FinalizeArgs {
@@ -177,6 +190,12 @@ hipError_t launch_short_clause(const ClausePassArgs& a, Tile t, int ks, int chun
 hipError_t launch_clause_pass(const ClausePassArgs& a, bool write_d, Tile t, int chunks,
                               hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, int F, hipStream_t s);
+// Flat plan (galsat_flat.hip): per-clause rows of every clause that is not
+// 3 literals long, then the variable pass (pairs + clause rows) and the
+// segments of split variables.
+hipError_t launch_row_clause(const ClausePassArgs& a, Tile t, int chunks, hipStream_t s);
+hipError_t launch_flat_var(const VarPassArgs& a, int mode, Tile t, int chunks, hipStream_t s);
+hipError_t launch_flat_seg(const VarPassArgs& a, Tile t, int chunks, hipStream_t s);
 hipError_t launch_init_state(float* x, int32_t ldx, int32_t n, int32_t R, uint64_t seed,
                              hipStream_t s);
 hipError_t launch_copy_state(const float* src, int32_t lds, float* dst, int32_t ldd, int32_t n,

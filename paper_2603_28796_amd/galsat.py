@@ -71,7 +71,8 @@ class _Info(ctypes.Structure):
         ("stored_lits", ctypes.c_int64), ("schedule", _I32), ("lanes_per_item", _I32),
         ("restarts_per_lane", _I32), ("var_chunks", _I32), ("clause_chunks", _I32),
         ("two_phase", _I32), ("xseq_chunks", _I32), ("device_bytes", ctypes.c_size_t), ("adam_step", _I32),
-        ("lds_restarts_per_group", _I32), ("lds_staged", _I32),
+        ("lds_restarts_per_group", _I32), ("lds_staged", _I32), ("flat", _I32),
+        ("clause_rows", _I32),
     ]
 
 
@@ -86,7 +87,7 @@ EXPORTS = ("galsat_default_options", "galsat_create", "galsat_destroy", "galsat_
            "galsat_status_string", "galsat_last_error")
 
 KERNEL_KINDS = ("var_pass", "clause_pass", "finalize", "copy", "pack", "count", "select",
-                "occ_pass", "var_sum")
+                "occ_pass", "var_sum", "seg_pass", "heavy")
 
 
 class _KernelTimes(ctypes.Structure):

@@ -147,7 +147,8 @@ def test_python_binding_fails_loudly_without_library(tmp_path):
 
 
 @pytest.mark.parametrize("plan", ["", "two=1", "two=0", "two=1,short=0", "two=1,wave=0",
-                                  "lpi=4,rpl=4", "lpi=16,rpl=1,two=1", "stream=1", "two=1,krec=4"])
+                                  "lpi=4,rpl=4", "lpi=16,rpl=1,two=1", "stream=1", "two=1,krec=4",
+                                  "flat=1", "flat=1,lpi=4,rpl=1", "flat=0"])
 @pytest.mark.parametrize("partials", [0, 1, 2])
 def test_planning_completes_for_every_plan(plan, partials):
     """galsat_create's host planning (records, chunk tables, partial-sum row

@@ -158,7 +158,7 @@ def test_sorted_item_orders(plan):
         a = Problem(cnf, R, recompute_max_len=4, plan_override=plan)
         inf = a.info()
         # the same plan in index order: same tile and gradient form
-        ref_plan = (f"two={inf['two_phase']},lpi={inf['lanes_per_item']},"
+        ref_plan = (f"two={inf['two_phase']},flat={inf['flat']},lpi={inf['lanes_per_item']},"
                     f"rpl={inf['restarts_per_lane']},dsort=0,csort=0")
         b = Problem(cnf, R, recompute_max_len=4, plan_override=ref_plan)
         x = _x0(cnf.n, R, 31)
@@ -240,7 +240,8 @@ def test_xcd_contiguous_order(case, chunks):
         a = Problem(cnf, R, plan_override=f"xseq={chunks}")
         inf = a.info()
         assert inf["xseq_chunks"] == chunks
-        tile = f"lpi={inf['lanes_per_item']},rpl={inf['restarts_per_lane']},two={inf['two_phase']}"
+        tile = (f"lpi={inf['lanes_per_item']},rpl={inf['restarts_per_lane']},"
+                f"two={inf['two_phase']},flat={inf['flat']}")
         b = Problem(cnf, R, plan_override=tile + ",xseq=0")
         x = _x0(cnf.n, R, 71)
         la, ga = a.loss_grad(x)
