@@ -9,16 +9,22 @@ with the hand-off (galsat_round_check: ballot/popcount count, best restart
 per formula and its assignment).  The state lives in HBM before the timed
 region starts.
 
-Prints ONE JSON line.  `value` = literal-evaluations per second
-(R * L * K / time), `roofline` = the dominant kernel's algorithmic bytes per
-launch over its event-timed average duration against the 8 TB/s HBM peak,
-`cpu_baseline` = the FP64 oracle on a bounded sample of the same workload.
+Headline workload: the uneven batch of 4,096 planted formulas (n_f from 50
+to 20,000, 32 restarts each): the largest of the five workloads and the one
+the batched-versus-plain comparison is defined on.  Two more legs run the
+single large formula (n = 1e7, 5 % clauses of 50-200 literals, R = 16) and
+planted 3-SAT n = 1e5 at R = 1,024.
+
+Prints ONE JSON line.  `value` = literal-evaluations per second of the
+headline (R * L * K / time), `roofline` = its dominant kernel's algorithmic
+bytes per launch over its event-timed average duration against the 8 TB/s
+HBM peak, `cpu_baseline` = the FP64 oracle on a bounded sample of the same
+workload (all host threads, and one thread).
 """
 import argparse
-import hashlib
+import ctypes
 import json
 import os
-import re
 import sys
 import time
 
@@ -28,58 +34,53 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "fwd+bwd literal-evals/s & % HBM peak; batched vs plain, 1e-5 rel vs FP64"
-# the sources that define the variable pass (its traffic figure is only
-# reported while these are unchanged since the counters were taken): the
-# device helpers, the pass itself and its argument struct
-CSRC = os.path.join(ROOT, "paper_2603_28796_amd", "csrc")
-KERNEL_SRC = [os.path.join(CSRC, f) for f in ("galsat_device.h", "galsat_varpass.hip")]
+HEADLINE = "batch4096"
+LEGS = ("large_n1e7", "planted3sat_n1e5")
+KERNEL_NAMES = {"var_pass": "k_flat_var", "clause_pass": "k_row_clause", "seg_pass": "k_flat_seg",
+                "heavy": "k_heavy_finish", "finalize": "k_finalize", "var_sum": "k_var_sum",
+                "occ_pass": "k_occ_pass"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for path in KERNEL_SRC:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
-    text = open(os.path.join(CSRC, "galsat_internal.h")).read()
-    start = text.index("struct VarPassArgs {")
-    h.update(text[start:text.index("};", start)].encode())
-    return h.hexdigest()[:16]
-
-
-def read_traffic(workload: str, kernel: str):
-    """Measured HBM bytes per launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
-    if not os.path.exists(path):
-        return None
-    text = open(path).read()
-    m_hash = re.search(r"kernel_source_sha256_16:\s*(\w+)", text)
-    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
-        return None
-    return float(m_bytes.group(1))
-
-
-def algorithmic_bytes(cnf, R, info, optimizer):
-    """Compulsory bytes the variable pass must move per launch: the
-    variable-major CSR, the clause-major CSR of the clauses it recomputes,
-    the stored partial rows it reads, x read once and the next x written
-    once (+ Adam moments read and written)."""
-    n, m, L = cnf.n, cnf.m, cnf.L
-    stored = int(info["stored_lits"])
-    krec = int(info["recompute_max_len"])
+def kernel_bytes(cnf, R, info, kind):
+    """Algorithmic bytes one step's launches of `kind` must move (each array
+    read or written once, no reuse assumed), for the flat plan:
+      var_pass     var_ptr, the pair records of the 3-literal clauses (the two
+                   other codes, 8 B per occurrence, the clause-major CSR's
+                   share), the clause-row records (4 B per occurrence), x
+                   read and the next x written (4nR each), every clause row
+                   read once (4R per row clause);
+      clause_pass  the clause-major CSR of the row clauses and their rows
+                   written (4R per row clause).
+    For the other plans the single pass counts both CSRs and x once (the
+    compulsory bytes M0 of m0_bytes) plus the stored partial rows read once."""
     import numpy as np
+    n, m, L = cnf.n, cnf.m, cnf.L
     lens = np.diff(cnf.clause_ptr)
-    rec = lens <= krec
-    m_rec, L_rec = int(rec.sum()), int(lens[rec].sum())
-    b = 4 * (n + 1) + 4 * L + 4 * (m_rec + 1) + 4 * L_rec + 8 * n * R + 4 * R * stored
-    if optimizer == "adam":
-        b += 16 * n * R
-    return b
+    if info.get("flat"):
+        row = (lens != 3) & (lens > 0)
+        m_r, L_r = int(row.sum()), int(lens[row].sum())
+        L3 = int(lens[lens == 3].sum())
+        if kind == "var_pass":
+            return 4 * (n + 1) + 8 * L3 + 4 * L_r + 8 * n * R + 4 * R * m_r
+        if kind == "clause_pass":
+            return 4 * (m_r + 1) + 4 * L_r + 4 * R * m_r
+        return None
+    if kind == "var_pass":
+        krec = int(info["recompute_max_len"])
+        rec = lens <= krec
+        return (4 * (n + 1) + 4 * L + 4 * (int(rec.sum()) + 1) + 4 * int(lens[rec].sum()) +
+                8 * n * R + 4 * R * int(info["stored_lits"]))
+    return None
+
+
+def m0_bytes(cnf, R):
+    """Compulsory bytes of a step: both CSR orientations once, x read once and
+    written once."""
+    return 8 * cnf.L + 4 * (cnf.m + 1) + 4 * (cnf.n + 1) + 8 * cnf.n * R
 
 
 def stream_copy_gbps(nbytes: int = 2 << 30, reps: int = 5) -> float:
@@ -104,89 +105,286 @@ def stream_copy_gbps(nbytes: int = 2 << 30, reps: int = 5) -> float:
 
 
 def cpu_model() -> str:
+    """Model name, with the x86 family / model / stepping numbers (which
+    identify the generation when the name is generic)."""
+    fields = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("model name", "cpu family", "model", "stepping") and k not in fields:
+                fields[k] = v.strip()
+            if len(fields) == 4:
+                break
     except OSError:
         pass
-    return "unknown"
+    if not fields:
+        return "unknown"
+    return (f"{fields.get('model name', '?')} (family {fields.get('cpu family', '?')}, "
+            f"model {fields.get('model', '?')}, stepping {fields.get('stepping', '?')})")
+
+
+def _omp_threads(k: int):
+    """Sets the OpenMP thread count of the process (the oracle's loops)."""
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+    except OSError:
+        pass
+
+
+def _sub_batch(cnf, count: int):
+    """The first `count` formulas of a batch as their own CNF."""
+    from paper_2603_28796_amd import inputs as I
+    if cnf.F == 1:
+        return cnf
+    return I.concat([cnf.sub(f) for f in range(min(count, cnf.F))], name=f"{cnf.name}[:{count}]")
 
 
 def cpu_baseline(cnf, R, lr, budget_s: float):
-    """The FP64 oracle's full step (gradient, unsat count, update) on the same
-    instance, all restarts, repeated until about budget_s seconds."""
+    """The FP64 oracle's full step (gradient, unsat count, update) on samples
+    of the same workload: all host threads, then one thread, each repeated
+    until about budget_s seconds."""
     import numpy as np
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    x = np.random.default_rng(0).random((R, cnf.n))
-    steps, t = 0, 0.0
-    while t < budget_s and steps < 20:
-        t0 = time.perf_counter()
-        _, _, _, x = oracle.full_step(cnf, x, lr)
-        t += time.perf_counter() - t0
-        steps += 1
-    v = R * cnf.L * steps / t
-    return {"value": v, "unit": "literal-evals/s", "cores": threads, "kind": "oracle",
-            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
-            "sample": f"{steps} full FP64 steps (all {R} restarts) of the same instance, "
-                      f"{t:.1f} s", "seconds": round(t, 2)}
+    out = {"unit": "literal-evals/s", "kind": "oracle", "cpu_model": cpu_model(),
+           "nproc": os.cpu_count()}
+    # sample sizes: the batch's first formulas (a quarter of it with all
+    # threads, 1/64 with one), a single formula whole
+    for label, k, frac in (("all", threads, 4), ("one", 1, 64)):
+        sample = _sub_batch(cnf, max(1, cnf.F // frac))
+        _omp_threads(k)
+        x = np.random.default_rng(0).random((R, sample.n))
+        steps, t = 0, 0.0
+        while t < budget_s and steps < 20:
+            t0 = time.perf_counter()
+            _, _, _, x = oracle.full_step(sample, x, lr)
+            t += time.perf_counter() - t0
+            steps += 1
+        v = R * sample.L * steps / t
+        desc = (f"{steps} full FP64 steps (all {R} restarts) of "
+                + (f"the first {sample.F} of the {cnf.F} formulas" if cnf.F > 1 else "the instance")
+                + f", {t:.1f} s")
+        if label == "all":
+            out.update({"value": v, "cores": k, "sample": desc, "seconds": round(t, 2)})
+        else:
+            out["one_thread"] = {"value": v, "cores": 1, "sample": desc, "seconds": round(t, 2)}
+        log(f"[bench] cpu baseline ({label}, {k} threads): {v:.4e} lit-evals/s ({desc})")
+    _omp_threads(threads)
+    return out
 
 
-def batched_vs_plain(steps: int):
-    """The uneven batch of 4,096 formulas (R=32): every formula in each launch
-    (the batched schedule, replayed from a captured graph) against one formula
-    at a time with a launch per pass per step and no graph, same kernels,
-    same steps, both from the same initial state in HBM."""
+def sampled_parity(prob, cnf, x, R, formulas=None, restarts=None):
+    """Loss, gradient and unsat counts of the GPU at the benchmarked state
+    against the oracle on a sample: formulas of a batch (all restarts), or
+    restarts of a single formula.  Reports the largest loss error relative
+    to the loss, the largest gradient error relative to |g| + sum|terms|
+    (the contract's scale), and unsat mismatches (must be 0)."""
+    import numpy as np
+    import torch
+    import oracle
+
+    loss, g = prob.loss_grad(x)
+    unsat, _, _ = prob.round_check(x, want_assign=False)
+    torch.cuda.synchronize()
+    worst_l, worst_g, bad_u, checked = 0.0, 0.0, 0, 0
+
+    def cmp(lg, gg, ug, sub, xs):
+        nonlocal worst_l, worst_g, bad_u, checked
+        lo_ref, g_ref, A = oracle.grad(sub, xs, with_abs=True)
+        lg = lg.astype(np.float64)
+        worst_l = max(worst_l, float(np.max(np.abs(lg - lo_ref) / np.maximum(lo_ref, 1e-30))))
+        worst_g = max(worst_g, float(np.max(np.abs(gg - g_ref) / np.maximum(np.abs(g_ref) + A, 1e-30))))
+        bad_u += int(np.sum(ug != oracle.unsat(sub, xs)))
+        checked += xs.shape[0]
+
+    if formulas is not None:
+        for f in formulas:
+            sub = cnf.sub(int(f))
+            v0, v1 = int(cnf.formula_var_begin[f]), int(cnf.formula_var_begin[f + 1])
+            xs = x[v0:v1, :R].double().cpu().t().contiguous().numpy()
+            gs = g[v0:v1, :R].double().cpu().t().contiguous().numpy()
+            cmp(loss[f:f + 1].cpu().numpy(), gs, unsat[f:f + 1].cpu().numpy(), sub, xs)
+        what = f"{len(formulas)} formulas x {R} restarts"
+    else:
+        for r in restarts:
+            xs = x[:, r:r + 1].double().cpu().t().contiguous().numpy()
+            gs = g[:, r:r + 1].double().cpu().t().contiguous().numpy()
+            cmp(loss[:, r:r + 1].cpu().numpy(), gs, unsat[:, r:r + 1].cpu().numpy(), cnf, xs)
+        what = f"restarts {list(restarts)}"
+    return {"sample": what, "max_loss_rel_err": worst_l, "max_grad_err_rel_to_scale": worst_g,
+            "unsat_mismatches": bad_u, "tolerance": 1e-5,
+            "pass": worst_l <= 1e-5 and worst_g <= 1e-5 and bad_u == 0}
+
+
+def time_steps(prob, cnf, R, x, K, W, graph=True):
+    """W warm-up steps, then K steps timed with events on the current stream
+    (graph-replayed when the handle captures one), ending with the hand-off."""
+    import torch
+
+    lt = torch.empty((max(K, W, 1), cnf.F, R), dtype=torch.float32, device="cuda")
+    ut = torch.empty((max(K, W, 1), cnf.F, R), dtype=torch.int32, device="cuda")
+    if W > 0:
+        prob.step(x, W, loss_trace=lt[:W], unsat_trace=ut[:W], trace=True)
+        prob.round_check(x)
+    if graph:
+        prob.prepare(x, K, loss_trace=lt[:K], unsat_trace=ut[:K])  # capture outside the timing
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    prob.step(x, K, loss_trace=lt[:K], unsat_trace=ut[:K], trace=True)
+    unsat, best, assign = prob.round_check(x)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    return ms, lt[:K], ut[:K], unsat
+
+
+def profile_kernels(prob, cnf, R, x, K):
+    """Per-kernel-kind launches and event-timed durations over K eager steps
+    (the library records HIP events on the launches' own stream)."""
+    import torch
+
+    lt = torch.empty((K, cnf.F, R), dtype=torch.float32, device="cuda")
+    ut = torch.empty((K, cnf.F, R), dtype=torch.int32, device="cuda")
+    prob.profile(True)
+    prob.step(x, K, loss_trace=lt, unsat_trace=ut, trace=True)
+    torch.cuda.synchronize()
+    kernels = prob.kernel_times()
+    prob.profile(False)
+    return kernels
+
+
+def roofline_of(cnf, R, info, kernels, K, step_ms):
+    """The dominant kernel's achieved rate of algorithmic bytes against the
+    HBM peak, plus the whole step's M0 rate.  When split hot variables make
+    the variable side three kernels (whole variables, segments, their
+    finish), the three are taken together as the variable pass: their
+    algorithmic bytes over the sum of their durations."""
+    if not kernels:
+        return None
+    kernels = dict(kernels)
+    side = [k for k in ("var_pass", "seg_pass", "heavy") if k in kernels]
+    if len(side) > 1:
+        kernels["var_side"] = (kernels["var_pass"][0], sum(kernels[k][1] for k in side))
+        for k in side:
+            del kernels[k]
+    kind, (launches, tot) = max(kernels.items(), key=lambda kv: kv[1][1])
+    names = dict(KERNEL_NAMES)
+    if not info.get("flat"):
+        names["var_pass"] = "k_var_pass"
+        names["seg_pass"] = "k_var_seg"
+    names["var_side"] = " + ".join(names[k] for k in side)
+    ab_step = kernel_bytes(cnf, R, info, "var_pass" if kind == "var_side" else kind)
+    m0 = m0_bytes(cnf, R)
+    out = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+           "kernel": names.get(kind, kind), "kernel_kind": kind,
+           "launches_per_step": launches / K, "avg_launch_ms": round(tot / launches, 5),
+           "kernel_share_of_step": round(tot / K / step_ms, 3),
+           "step_M0_bytes": m0, "step_M0_frac": round(m0 / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if ab_step is None:
+        out.update({"achieved": None, "frac": None, "algorithmic_bytes_per_launch": None})
+        return out
+    ab = ab_step * K / launches
+    achieved = ab / (tot / launches / 1e3) / 1e9
+    out.update({"achieved": round(achieved, 2), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes_per_launch": ab})
+    return out
+
+
+def run_workload(key, K, W, args, parity=True):
+    """Generate, plan, time K steps, profile kernels and check a sample
+    against the oracle.  Returns (result dict, cnf, problem)."""
+    import numpy as np
     import torch
 
     from paper_2603_28796_amd import inputs as I
     from paper_2603_28796_amd.galsat import Problem
 
-    w = I.WORKLOADS["batch4096"]
+    w = I.WORKLOADS[key]
     t0 = time.perf_counter()
     cnf = w.make()
-    log(f"[bench] batch workload: F={cnf.F} n={cnf.n} L={cnf.L} "
+    log(f"[bench] workload {w.key}: n={cnf.n} m={cnf.m} L={cnf.L} F={cnf.F} R={w.restarts} "
         f"(generated in {time.perf_counter() - t0:.1f} s)")
     R = w.restarts
-    out = {"workload": w.key, "formulas": cnf.F, "restarts": R, "steps": steps}
-    x0 = None
-    for name, sched, graph in (("batched", "general", True), ("plain", "plain", False)):
-        prob = Problem(cnf, R, lr=w.lr, schedule=sched, use_graph=graph)
-        if x0 is None:
-            x0 = prob.init_state(I.SEED_BASE + 4)
+    partials = {0: "auto", 1: "store", 2: "recompute"}[w.recompute]
+    plan, plan_source, tuned_ms = args.plan, "plan_override" if args.plan else "rules", None
+    if args.autotune and not args.plan:
+        # the autotuner times its candidate plans (the rule plan among them)
+        # from the benchmark's initial state and the fastest is benchmarked
+        from paper_2603_28796_amd.galsat import autotune
+        t0 = time.perf_counter()
+        rule = Problem(cnf, R, lr=w.lr, partials=partials, schedule=args.schedule)
+        x0 = rule.init_state(I.SEED_BASE + 2)
+        rule.close()
+        plan, tuned_ms = autotune(cnf, R, x0, steps=2, lr=w.lr, partials=partials,
+                                  schedule=args.schedule)
+        plan_source = "galsat_autotune"
+        del x0
+        torch.cuda.empty_cache()
+        log(f"[bench] autotuned plan for {key}: {plan} ({tuned_ms:.3f} ms/step, "
+            f"{time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    prob = Problem(cnf, R, lr=w.lr, partials=partials, plan_override=plan,
+                   use_graph=bool(args.graph), schedule=args.schedule)
+    info = prob.info()
+    log(f"[bench] plan ({time.perf_counter() - t0:.1f} s): {info}")
+    x = prob.init_state(I.SEED_BASE + 2)
+    ms, lt, ut, unsat = time_steps(prob, cnf, R, x, K, W, graph=bool(args.graph))
+    value = R * cnf.L * K / (ms / 1e3)
+    log(f"[bench] {key}: {K} steps {ms:.2f} ms ({ms / K:.4f} ms/step), {value:.4e} lit-evals/s; "
+        f"min unsat {int(unsat.min())}")
+    res = {"workload": key, "description": w.description, "n": cnf.n, "m": cnf.m, "L": cnf.L,
+           "formulas": cnf.F, "restarts": R, "lr": w.lr, "partials": partials,
+           "steps": K, "ms_per_step": ms / K, "lit_evals_per_s": value,
+           "min_unsat_after": int(unsat.min()),
+           "plan": {k: info[k] for k in ("schedule", "flat", "two_phase", "lanes_per_item",
+                                         "restarts_per_lane", "var_chunks", "clause_chunks",
+                                         "clause_rows", "recompute_max_len")},
+           "plan_override": plan, "plan_source": plan_source, "autotune_ms_per_step": tuned_ms}
+    if not args.no_profile:
+        kernels = profile_kernels(prob, cnf, R, x, min(K, 5))
+        log(f"[bench] {key} kernel times: {kernels}")
+        res["kernel_ms_per_step"] = {k: round(v[1] / min(K, 5), 4) for k, v in kernels.items()}
+        res["roofline"] = roofline_of(cnf, R, info, kernels, min(K, 5), ms / K)
+    if parity and not args.no_parity:
+        if cnf.F > 1:
+            fs = np.r_[0, np.random.default_rng(3).choice(cnf.F, 6, replace=False), cnf.F - 1]
+            res["parity"] = sampled_parity(prob, cnf, x, R, formulas=fs)
+        else:
+            res["parity"] = sampled_parity(prob, cnf, x, R, restarts=[0, R - 1])
+        log(f"[bench] {key} parity: {res['parity']}")
+    return res, cnf, prob
+
+
+def plain_legs(cnf, R, lr, x0, steps):
+    """One formula at a time (a launch per pass per step), eager and replayed
+    from a captured graph, from the same state as the batched run."""
+    import torch
+
+    from paper_2603_28796_amd.galsat import Problem
+
+    out = {}
+    for name, graph in (("plain_eager", False), ("plain_graph", True)):
+        prob = Problem(cnf, R, lr=lr, schedule="plain", use_graph=graph)
         x = x0.clone()
-        lt = torch.empty((steps, cnf.F, R), dtype=torch.float32, device="cuda")
-        ut = torch.empty((steps, cnf.F, R), dtype=torch.int32, device="cuda")
-        prob.step(x, 1, loss_trace=lt[:1], unsat_trace=ut[:1], trace=True)  # warm-up
-        torch.cuda.synchronize()
-        log(f"[bench] {name}: warm-up step done")
-        x = x0.clone()
-        if graph:
-            prob.prepare(x, steps, loss_trace=lt, unsat_trace=ut)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        prob.step(x, steps, loss_trace=lt, unsat_trace=ut, trace=True)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
+        ms, _, _, _ = time_steps(prob, cnf, R, x, steps, 1, graph=graph)
         out[f"{name}_ms_per_step"] = ms / steps
-        out[f"{name}_lit_evals_per_s"] = R * cnf.L * steps / (ms / 1e3)
         log(f"[bench] {name}: {ms / steps:.3f} ms/step")
         prob.close()
-    out["speedup"] = out["plain_ms_per_step"] / out["batched_ms_per_step"]
+        del x
+        torch.cuda.synchronize()
     return out
 
 
 def gumbel_and_handoff(cnf, R, steps: int):
-    """The paper's own optimizer loop on the same instance (straight-through
-    Gumbel-softmax, Adam lr 0.5, tau 1), then the hand-off to the CPU stage:
-    100 candidates (Eq. 8), the top 0.05 % confident variables of each as
-    unit literals (Eq. 9-10) and the 7 least confident of the selected
-    restart as branching variables (Lemma 1).  Event-timed on the current
-    stream, inputs resident in HBM."""
+    """The paper's own optimizer loop (straight-through Gumbel-softmax, Adam
+    lr 0.5, tau 1), then the hand-off to the CPU stage: 100 candidates
+    (Eq. 8), the top 0.05 % confident variables of each as unit literals
+    (Eq. 9-10) and the 7 least confident of the selected restart as branching
+    variables (Lemma 1).  Event-timed on the current stream."""
     import torch
 
     from paper_2603_28796_amd import inputs as I
@@ -211,8 +409,8 @@ def gumbel_and_handoff(cnf, R, steps: int):
     e[3].record()
     torch.cuda.synchronize()
     ms = e[0].elapsed_time(e[1])
-    out = {"optimizer": "adam", "lr": 0.5, "tau": 1.0, "steps": steps, "restarts": R,
-           "ms_per_step": ms / steps, "lit_evals_per_s": R * cnf.L * steps / (ms / 1e3),
+    out = {"workload": cnf.name, "optimizer": "adam", "lr": 0.5, "tau": 1.0, "steps": steps,
+           "restarts": R, "ms_per_step": ms / steps, "lit_evals_per_s": R * cnf.L * steps / (ms / 1e3),
            "min_unsat_first_step": int(ut[0].min()), "min_unsat_last_step": int(ut[-1].min()),
            "handoff": {"candidates": 100, "ms": e[2].elapsed_time(e[3]),
                        "unit_literals_per_candidate": int(off_u[-1]),
@@ -224,23 +422,27 @@ def gumbel_and_handoff(cnf, R, steps: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="planted3sat_n1e5")
-    ap.add_argument("--partials", default=None, help="auto | store | recompute")
-    ap.add_argument("--plan", default=None, help="plan override, e.g. lpi=64,rpl=4")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel run")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=HEADLINE)
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="further workloads, each timed and checked like the headline ('' for none)")
+    ap.add_argument("--leg-steps", type=int, default=20)
+    ap.add_argument("--plan", default=None, help="plan override, e.g. lpi=8,rpl=4")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="benchmark the plan galsat_autotune picks (its candidates include the "
+                         "rule plan); 0: the rule plan")
     ap.add_argument("--graph", type=int, default=1, help="replay the step loop from a hipGraph")
     ap.add_argument("--schedule", default="auto", help="auto | general | lds | plain")
-    ap.add_argument("--batch-steps", type=int, default=20,
-                    help="steps of the batched vs one-formula-at-a-time comparison (0: skip)")
-    ap.add_argument("--gumbel-steps", type=int, default=50,
-                    help="steps of the straight-through Gumbel loop + hand-off timing (0: skip)")
-    ap.add_argument("--tseitin", type=int, default=0,
-                    help="run the workload after chain normalization to this clause width "
-                         "(Eq. 6-7); also reports the unsat count on the original clauses")
+    ap.add_argument("--plain-steps", type=int, default=5,
+                    help="steps of the one-formula-at-a-time legs of a batch workload (0: skip)")
+    ap.add_argument("--gumbel-steps", type=int, default=30,
+                    help="steps of the straight-through Gumbel loop + hand-off on planted3sat_n1e5 "
+                         "(0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel run")
+    ap.add_argument("--no-parity", action="store_true", help="skip the sampled oracle checks")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -250,145 +452,74 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2603_28796_amd import inputs as I
-    from paper_2603_28796_amd.galsat import Problem
-
-    w = I.WORKLOADS[args.workload]
-    t0 = time.perf_counter()
-    cnf = w.make()
-    original = None
-    if args.tseitin:
-        from paper_2603_28796_amd.galsat import tseitin
-        original = cnf
-        cnf = tseitin(cnf, args.tseitin)
-        log(f"[bench] width-{args.tseitin} normalization: n {original.n} -> {cnf.n}, "
-            f"m {original.m} -> {cnf.m}, L {original.L} -> {cnf.L}")
-    log(f"[bench] workload {w.key}: n={cnf.n} m={cnf.m} L={cnf.L} F={cnf.F} R={w.restarts} "
-        f"(generated in {time.perf_counter() - t0:.1f} s)")
-    R = w.restarts
-    partials = args.partials or {0: "auto", 1: "store", 2: "recompute"}[w.recompute]
     torch.cuda.set_device(0)
-    prob = Problem(cnf, R, lr=w.lr, partials=partials, plan_override=args.plan,
-                   use_graph=bool(args.graph), schedule=args.schedule)
-    info = prob.info()
-    log(f"[bench] plan: {info}")
-    x = prob.init_state(I.SEED_BASE + 2)
     K, W = args.steps, args.warmup
-    FR = cnf.F * R
-    lt = torch.empty((max(K, W), cnf.F, R), dtype=torch.float32, device="cuda")
-    ut = torch.empty((max(K, W), cnf.F, R), dtype=torch.int32, device="cuda")
-
-    if W > 0:
-        prob.step(x, W, loss_trace=lt[:W], unsat_trace=ut[:W], trace=True)
-        prob.round_check(x)
-    if args.graph:
-        prob.prepare(x, K, loss_trace=lt[:K], unsat_trace=ut[:K])  # capture outside the timing
-    torch.cuda.synchronize()
-    log(f"[bench] warmup {W} steps done")
-
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    prob.step(x, K, loss_trace=lt[:K], unsat_trace=ut[:K], trace=True)
-    unsat, best, assign = prob.round_check(x)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    value = R * cnf.L * K / (ms / 1e3)
-    log(f"[bench] timed {K} steps: {ms:.2f} ms ({ms / K:.4f} ms/step), {value:.4e} lit-evals/s; "
-        f"min unsat {int(unsat.min())}, final mean loss {float(lt[K - 1].mean()):.3f}")
-    normalized = None
-    if original is not None:
-        # the original variables keep their ids: round them and count the
-        # original clauses they leave unsatisfied
-        orig_prob = Problem(original, R, lr=w.lr)
-        u0, _, _ = orig_prob.round_check(x[:original.n])
-        torch.cuda.synchronize()
-        normalized = {"width": args.tseitin, "original_n": original.n, "original_m": original.m,
-                      "original_L": original.L, "min_unsat_original": int(u0.min()),
-                      "min_unsat_normalized": int(unsat.min()),
-                      "original_lit_evals_per_s": R * original.L * K / (ms / 1e3)}
-        log(f"[bench] normalized run: {normalized}")
-        orig_prob.close()
-
-    roofline = None
-    kernels = None
-    if not args.no_profile:
-        prob.profile(True)
-        prob.step(x, K, loss_trace=lt[:K], unsat_trace=ut[:K], trace=True)
-        prob.round_check(x)
-        torch.cuda.synchronize()
-        kernels = prob.kernel_times()
-        prob.profile(False)
-        log(f"[bench] kernel times: {kernels}")
-        launches, tot = kernels.get("var_pass", (0, 0.0))
-        # the LDS schedule runs every step in one launch with the state held
-        # in LDS between steps: no per-step HBM roofline applies to it
-        if launches and info["schedule"] != "lds":
-            # the pass may be split into several launches per step (restart
-            # tile groups): each launch moves its share of the step's bytes
-            per_step = launches / K
-            avg_ms = tot / launches
-            ab = algorithmic_bytes(cnf, R, info, "sgd") / per_step
-            achieved = ab / (avg_ms / 1e3) / 1e9
-            traffic = read_traffic(w.key, "var_pass")
-            copy = stream_copy_gbps()
-            roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": traffic, "kernel": "k_var_pass",
-                        "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_ms, 5),
-                        "launches_per_step": per_step,
-                        # measured traffic rate and a measured copy on the same GPU
-                        "traffic_GBps": round(traffic / (avg_ms / 1e3) / 1e9, 1) if traffic else None,
-                        "stream_copy_GBps": round(copy, 1)}
-
-    gumbel = None
-    if args.gumbel_steps > 0 and not args.tseitin:
-        prob.close()  # free the SGD handle's workspace first
-        gumbel = gumbel_and_handoff(cnf, R, args.gumbel_steps)
-        log(f"[bench] gumbel-ST + hand-off: {gumbel}")
-
+    head, cnf, prob = run_workload(args.workload, K, W, args)
+    R = head["restarts"]
     batch = None
-    if args.batch_steps > 0:
-        batch = batched_vs_plain(args.batch_steps)
-
+    if cnf.F > 1 and args.plain_steps > 0:
+        from paper_2603_28796_amd import inputs as I
+        x0 = prob.init_state(I.SEED_BASE + 4)
+        prob.close()
+        batch = {"batched_ms_per_step": head["ms_per_step"]}
+        batch.update(plain_legs(cnf, R, head["lr"], x0, args.plain_steps))
+        batch["speedup_vs_plain_eager"] = batch["plain_eager_ms_per_step"] / head["ms_per_step"]
+        batch["speedup_vs_plain_graph"] = batch["plain_graph_ms_per_step"] / head["ms_per_step"]
+        batch["gate"] = ("the >= 5x target is read against plain_eager (a launch per pass per "
+                         "formula per step, the plain method); plain_graph replays the same "
+                         "launches from a captured graph")
+        del x0
+    else:
+        prob.close()
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline (oracle, ~{args.cpu_seconds:.0f} s)")
-        cpu = cpu_baseline(cnf, R, w.lr, args.cpu_seconds)
-        log(f"[bench] cpu baseline: {cpu}")
+        cpu = cpu_baseline(cnf, R, head["lr"], args.cpu_seconds)
+    del cnf
+    torch.cuda.empty_cache()
 
+    legs = {}
+    for key in [k for k in args.legs.split(",") if k and k != args.workload]:
+        res, lcnf, lprob = run_workload(key, args.leg_steps, 2, args)
+        lprob.close()
+        if key == "planted3sat_n1e5" and args.gumbel_steps > 0:
+            res["gumbel_st"] = gumbel_and_handoff(lcnf, res["restarts"], args.gumbel_steps)
+            log(f"[bench] gumbel-ST + hand-off: {res['gumbel_st']}")
+        legs[key] = res
+        del lcnf
+        torch.cuda.empty_cache()
+
+    copy = stream_copy_gbps()
+    roof = head.get("roofline")
+    if roof is not None:
+        roof["stream_copy_GBps"] = round(copy, 1)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["lit_evals_per_s"],
         "unit": "literal-evals/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": ms / K,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.key + (f"/width{args.tseitin}" if args.tseitin else ""),
-                   "description": w.description, "n": cnf.n, "m": cnf.m,
-                   "L": cnf.L, "formulas": cnf.F, "restarts": R, "lr": w.lr, "partials": partials,
-                   "schedule": info["schedule"], "lanes_per_item": info["lanes_per_item"],
-                   **({"lds_restarts_per_group": info["lds_restarts_per_group"],
-                       "lds_staged": info["lds_staged"]} if info["schedule"] == "lds" else {}),
-                   "restarts_per_lane": info["restarts_per_lane"]},
-        "roofline": roofline,
+        "config": {"workload": head["workload"], "description": head["description"],
+                   "n": head["n"], "m": head["m"], "L": head["L"], "formulas": head["formulas"],
+                   "restarts": R, "lr": head["lr"], "partials": head["partials"],
+                   "plan": head["plan"], "plan_override": head["plan_override"],
+                   "plan_source": head["plan_source"]},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "batched_vs_plain": batch,
-        "normalized": normalized,
-        "gumbel_st": gumbel,
-        "kernel_ms": {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 5)}
-                      for k, v in (kernels or {}).items()},
+        "parity": head.get("parity"),
+        "kernel_ms_per_step": head.get("kernel_ms_per_step"),
+        "min_unsat_after": head["min_unsat_after"],
+        "legs": legs,
+        "stream_copy_GBps": round(copy, 1),
     }
     print(json.dumps(out), flush=True)
 

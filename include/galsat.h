@@ -346,11 +346,15 @@ galsat_status galsat_round_check_static(galsat_handle h, const float* x, int32_t
  * correction.  For checkpoint and resume. */
 galsat_status galsat_set_adam_step(galsat_handle h, int32_t t);
 
-/* Plan autotuner.  Derives candidate plans from the restart count (lanes
- * per item and restarts per lane), the clause-length histogram (recompute
- * threshold when clauses longer than 8 literals exist), the formula
- * count (chunks per formula of the XCD-aware order) and, for at most 64
- * restarts, single pass against two-phase gradient; with the LDS schedule
+/* Plan autotuner.  With at most 64 restarts and AUTO partials (no
+ * recompute_max_len) the candidates are the flat gradient with and without
+ * record prefetch, with 20 and 80 chunks per formula for batches, and the
+ * two-phase gradient.  Otherwise it derives candidate plans from the
+ * restart count (lanes per item and restarts per lane), the clause-length
+ * histogram (recompute threshold when clauses longer than 8 literals
+ * exist), the formula count (chunks per formula of the XCD-aware order)
+ * and, for at most 64 restarts, single pass against two-phase gradient;
+ * with the LDS schedule
  * instead its restarts per workgroup (1 to 32, up to the restarts rounded
  * to a power of two), records staged or not; creates a handle for
  * each, times `steps` steps of galsat_step from a copy of x0 with HIP

@@ -247,7 +247,9 @@ __device__ __forceinline__ void inline4_products(const VarPassArgs& a, const int
 
 // The epilogue for one variable row: projected SGD or Adam update (writing
 // the next state) or the (upstream-scaled) gradient.
-template <int RPL, int MODE>
+// NT: the output row is stored non-temporally (it is not read again in the
+// same pass, so it should not evict rows that are).
+template <int RPL, int MODE, bool NT = false>
 __device__ __forceinline__ void var_epilogue(const VarPassArgs& a, int v, int r0,
                                              const float (&xv)[RPL], const double (&g)[RPL]) {
   float o[RPL];
@@ -281,7 +283,8 @@ __device__ __forceinline__ void var_epilogue(const VarPassArgs& a, int v, int r0
       o[j] = (float)(w * g[j]);
     }
   }
-  store_row<RPL>(a.out + (int64_t)v * a.ldo + r0, o);
+  if constexpr (NT) store_row_nt<RPL>(a.out + (int64_t)v * a.ldo + r0, o);
+  else store_row<RPL>(a.out + (int64_t)v * a.ldo + r0, o);
 }
 
 // SplitMix64 output mixing (the finalizer of Steele, Lea and Flood's

@@ -29,8 +29,9 @@
 // underflow it midway.
 //
 // Sums run in a fixed order, so results are bitwise reproducible: per
-// variable the first-literal pairs, then the other pairs, then the clause
-// rows, each in variable-major slot order, accumulated in FP64.
+// variable the first-literal pairs (positive own literals, then negated),
+// then the other pairs, each in variable-major slot order, then the clause
+// rows (positive, then negated), each in row order, accumulated in FP64.
 #include "galsat_device.h"
 
 namespace galsat {
@@ -84,13 +85,6 @@ __device__ __forceinline__ void store_urow(uint32_t* __restrict__ p, const uint3
   }
 }
 
-// Row of a formula-local literal code: the formula's rows start at xb.
-template <int RPL>
-__device__ __forceinline__ void load_local(const float* xb, int32_t ldx, int code, int rc,
-                                           float (&o)[RPL]) {
-  load_row<RPL>(xb + (int64_t)((uint32_t)code >> 1) * ldx + rc, o);
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------- row pass
@@ -136,6 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_row_clause(ClausePassArgs a) {
         codes[u] = ldc(a.clause_lits, pu);
         load_row<RPL>(a.x + (int64_t)(codes[u] >> 1) * a.ldx + rc, y[u]);
       }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const bool use = p + u < pe;
@@ -174,112 +169,203 @@ __global__ __launch_bounds__(kBlock) void k_row_clause(ClausePassArgs a) {
 }
 
 // ------------------------------------------------------------ variable side
+//
+// Rows are addressed by 32-bit byte offsets from the base of their formula
+// (the plan keeps a formula's state and clause rows below 4 GiB and its
+// local indices below 2^24), so each gather costs one 24-bit multiply-add
+// and the load takes its base from scalar registers.  Record streams are
+// read once per step and are loaded non-temporally, and so is the next
+// state stored, so the gathered rows keep the L2.
+
+__device__ __forceinline__ uint32_t row_off(uint32_t idx, uint32_t stride_bytes, uint32_t col_bytes) {
+  return __umul24(idx, stride_bytes) + col_bytes;
+}
 
 // Pair records of [b, e) (consecutive pair slots of one variable), four at a
-// time with all eight row gathers in flight.  FIRST: the own literal is its
-// clause's first, so the occurrence also accounts for U_t = a_own * f1 * f2
-// and the clause's rounded satisfaction.
-template <int RPL, bool FIRST>
-__device__ __forceinline__ void flat_pairs(const VarPassArgs& a, const float* xb, int b, int e,
-                                           int rc, const float (&xv)[RPL], double (&g)[RPL],
+// time with all eight row gathers in flight.  A literal's factor is one FMA,
+// fma(y, +1, 0) = y for a negated literal and fma(y, -1, 1) = 1 - y for a
+// positive one (each rounded once, as 1 - y is).  The four contributions are
+// summed in FP32 and that sum is added to the FP64 accumulator; a record
+// past the end has weight 0.  The own literal's sign is the first code's
+// bit 31.  FIRST: the own literal is its clause's first, so the occurrence
+// also accounts for U_t = a_own * f1 * f2 and the clause's rounded
+// satisfaction: unsatisfied when all three literals are false, a literal
+// being false when f >= 0.5 (positive) or f > 0.5, i.e. f >= 0.5 + 2^-24
+// (negated).
+template <int RPL, bool FIRST, bool PF>
+__device__ __forceinline__ void flat_pairs(const VarPassArgs& a, const char* xb, uint32_t ldx4,
+                                           uint32_t rc4, int b, int e, const float (&ap)[RPL],
+                                           const float (&an)[RPL], double (&g)[RPL],
                                            double (&lsum)[RPL], int (&usum)[RPL]) {
+  if (b >= e) return;
+  bool fp[RPL], fn[RPL];  // own literal false (first-literal loop only)
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      fp[j] = ap[j] >= kHalf;
+      fn[j] = an[j] >= kHalfUp;
+    }
+  }
+  const long long* pr = reinterpret_cast<const long long*>(a.pairs);
+  // PF: records of the next batch are loaded while this batch's gathers are
+  // in flight (indices clamped into [b, e), so every load stays in bounds)
+  long long nxt[4];
+  if constexpr (PF) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nxt[k] = __builtin_nontemporal_load(pr + (b + k < e ? b + k : e - 1));
+  }
   for (int q = b; q < e; q += 4) {
-    int2 rec[4];
+    uint32_t c1[4], c2[4];
     float y[4][2][RPL];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int qk = q + k < e ? q + k : e - 1;  // in bounds; masked below
-      const int32_t* rp = reinterpret_cast<const int32_t*>(a.pairs) + 2 * (int64_t)qk;
-      rec[k] = make_int2(ldc(rp, 0), ldc(rp, 1));
-      load_local<RPL>(xb, a.ldx, rec[k].x & 0x7fffffff, rc, y[k][0]);
-      load_local<RPL>(xb, a.ldx, rec[k].y, rc, y[k][1]);
+      if constexpr (!PF) nxt[k] = __builtin_nontemporal_load(pr + (q + k < e ? q + k : e - 1));
+      c1[k] = (uint32_t)nxt[k];
+      c2[k] = (uint32_t)((unsigned long long)nxt[k] >> 32);
+      load_row<RPL>(reinterpret_cast<const float*>(xb + row_off((c1[k] & 0x7fffffffu) >> 1, ldx4, rc4)),
+                    y[k][0]);
+      load_row<RPL>(reinterpret_cast<const float*>(xb + row_off(c2[k] >> 1, ldx4, rc4)), y[k][1]);
     }
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        nxt[k] = __builtin_nontemporal_load(pr + (q + 4 + k < e ? q + 4 + k : e - 1));
+    }
+    // every gather of the batch is issued before any of them is used
+    __builtin_amdgcn_sched_barrier(0);
+    float tg[RPL], tl[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) { tg[j] = 0.0f; tl[j] = 0.0f; }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const bool use = q + k < e;
-      const int c1 = rec[k].x & 0x7fffffff, c2 = rec[k].y;
-      const bool own_neg = rec[k].x < 0;
+      const bool own_neg = (c1[k] >> 31) != 0;
+      const bool n1 = (c1[k] & 1) != 0, n2 = (c2[k] & 1) != 0;
+      const float sg1 = n1 ? 1.0f : -1.0f, sb1 = n1 ? 0.0f : 1.0f;
+      const float sg2 = n2 ? 1.0f : -1.0f, sb2 = n2 ? 0.0f : 1.0f;
+      const float w = use ? (own_neg ? 1.0f : -1.0f) : 0.0f;
+      const float th1 = n1 ? kHalfUp : kHalf, th2 = n2 ? kHalfUp : kHalf;
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
-        const float f1 = lit_factor(c1, y[k][0][j]), f2 = lit_factor(c2, y[k][1][j]);
+        const float f1 = fmaf(y[k][0][j], sg1, sb1), f2 = fmaf(y[k][1][j], sg2, sb2);
         const float p = f1 * f2;
-        g[j] += use ? (double)(own_neg ? p : -p) : 0.0;
+        tg[j] = fmaf(w, p, tg[j]);
         if constexpr (FIRST) {
-          const float ao = own_neg ? xv[j] : 1.0f - xv[j];
-          lsum[j] += use ? (double)(ao * p) : 0.0;
-          const float m = fminf(fminf(false_margin(c1, f1), false_margin(c2, f2)),
-                                false_margin(own_neg ? 1 : 0, ao));
-          usum[j] += (use && m >= 0.0f) ? 1 : 0;
+          const float ao = own_neg ? an[j] : ap[j];
+          tl[j] = fmaf(use ? 1.0f : 0.0f, ao * p, tl[j]);
+          const bool own_false = own_neg ? fn[j] : fp[j];
+          usum[j] += (use && own_false && f1 >= th1 && f2 >= th2) ? 1 : 0;
         }
       }
+    }
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      g[j] += (double)tg[j];
+      if constexpr (FIRST) lsum[j] += (double)tl[j];
     }
   }
 }
 
-// Clause-row records of [b, e): record = row | own_neg << 31.  The partial
-// of the occurrence is the row's product divided by the own factor (count
-// 0), the row's product when the own factor is its only zero, else 0; the
-// sign of dU/dx_v (- for a positive own literal, + for a negated one) is
-// folded into the inverse.
-template <int RPL>
-__device__ __forceinline__ void flat_rows(const VarPassArgs& a, int b, int e, int rc,
-                                          const float (&xv)[RPL], double (&g)[RPL]) {
+// 1/a in FP64 for a nonzero FP32 factor a (always a normal FP64 number):
+// the hardware reciprocal refined by two Newton steps, far below the
+// FP32 rounding of the final gradient.
+__device__ __forceinline__ double recip64(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(fma(-a, r, 1.0), r, r);
+  return fma(fma(-a, r, 1.0), r, r);
+}
+
+// Clause-row records of [b, e): record = row within the formula; records
+// before m belong to positive own literals, the rest to negated ones (the
+// plan keeps a variable's positive-literal rows first).  With a the own
+// factor, the partial is Q / a when the clause has no zero factor, Q when a
+// is its only zero, and 0 otherwise; dU/dx_v carries the sign s (-1 for a
+// positive own literal, +1 for a negated one), folded into the inverse.  A
+// zero own factor with the one-zero flag clear means two or more zeros,
+// whose stored Q is 0, so only "flag set and own factor nonzero" needs
+// masking.
+template <int RPL, bool PF>
+__device__ __forceinline__ void flat_rows(const VarPassArgs& a, const char* qb, uint32_t ldq4,
+                                          uint32_t rc4, int b, int m, int e,
+                                          const float (&ap)[RPL], const float (&an)[RPL],
+                                          double (&g)[RPL]) {
   if (b >= e) return;
   double inv_p[RPL], inv_n[RPL];
-  bool zp[RPL], zn[RPL];
+  uint32_t nz_p[RPL], nz_n[RPL];  // all ones when the own factor is nonzero
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
-    const float ap = 1.0f - xv[j], an = xv[j];
-    zp[j] = ap == 0.0f;
-    zn[j] = an == 0.0f;
-    inv_p[j] = zp[j] ? -1.0 : -1.0 / (double)ap;
-    inv_n[j] = zn[j] ? 1.0 : 1.0 / (double)an;
+    const bool zp = ap[j] == 0.0f, zn = an[j] == 0.0f;
+    nz_p[j] = zp ? 0u : ~0u;
+    nz_n[j] = zn ? 0u : ~0u;
+    inv_p[j] = zp ? -1.0 : -recip64((double)ap[j]);
+    inv_n[j] = zn ? 1.0 : recip64((double)an[j]);
   }
-  constexpr int B = 8;
+  constexpr int B = 4;
+  uint32_t nxt[B];  // PF: records of the next batch, loaded during this one's gathers
+  if constexpr (PF) {
+#pragma unroll
+    for (int k = 0; k < B; ++k) nxt[k] = __builtin_nontemporal_load(a.lrec + (b + k < e ? b + k : e - 1));
+  }
   for (int q = b; q < e; q += B) {
     uint32_t rec[B];
     uint32_t u[B][RPL];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      const int qk = q + k < e ? q + k : e - 1;  // in bounds; masked below
-      rec[k] = (uint32_t)ldc(reinterpret_cast<const int32_t*>(a.lrec), qk);
-      load_urow<RPL>(a.qrow + (int64_t)(rec[k] & 0x7fffffffu) * a.ldq + rc, u[k]);
+      if constexpr (!PF) nxt[k] = __builtin_nontemporal_load(a.lrec + (q + k < e ? q + k : e - 1));
+      rec[k] = nxt[k];
+      load_urow<RPL>(reinterpret_cast<const uint32_t*>(qb + row_off(rec[k], ldq4, rc4)), u[k]);
     }
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 0; k < B; ++k)
+        nxt[k] = __builtin_nontemporal_load(a.lrec + (q + B + k < e ? q + B + k : e - 1));
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      const bool use = q + k < e;
-      const bool own_neg = (rec[k] >> 31) != 0;
+      const uint32_t keep = q + k < e ? ~0u : 0u;
+      const bool own_neg = q + k >= m;
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
-        const bool one_zero = (u[k][j] >> 31) != 0;
-        const bool own_zero = own_neg ? zn[j] : zp[j];
-        const double qv = (one_zero && !own_zero) ? 0.0 : clause_value(u[k][j]);
-        const double s = own_neg ? inv_n[j] : inv_p[j];
-        g[j] += use ? qv * s : 0.0;
+        // high word of the FP64 value: the 31 stored bits shifted past the
+        // flag; cleared when masked (the low word is always 0)
+        const uint32_t skip = (uint32_t)((int32_t)u[k][j] >> 31) & (own_neg ? nz_n[j] : nz_p[j]);
+        const uint32_t hi = (u[k][j] << 1) & ~skip & keep;
+        g[j] = fma(__hiloint2double((int)hi, 0), own_neg ? inv_n[j] : inv_p[j], g[j]);
       }
     }
   }
 }
 
 // Unified index range [u0, u1) of variable v's contributions: first-literal
-// pairs, then the other pairs, then clause rows (the three together have
-// exactly one entry per occurrence of v).
-template <int RPL>
-__device__ __forceinline__ void flat_range(const VarPassArgs& a, const float* xb, int v, int u0,
-                                           int u1, int rc, const float (&xv)[RPL],
+// pairs (positive own literal, then negated), the other pairs, then clause
+// rows (positive, then negated): together exactly one entry per occurrence
+// of v.  xb, qb: the bases of v's
+// formula's state rows and clause rows.
+template <int RPL, bool PF>
+__device__ __forceinline__ void flat_range(const VarPassArgs& a, const char* xb, const char* qb,
+                                           int v, int u0, int u1, int rc, const float (&xv)[RPL],
                                            double (&g)[RPL], double (&lsum)[RPL],
                                            int (&usum)[RPL]) {
+  const uint32_t ldx4 = (uint32_t)a.ldx * 4u, ldq4 = (uint32_t)a.ldq * 4u, rc4 = (uint32_t)rc * 4u;
+  float ap[RPL], an[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    ap[j] = 1.0f - xv[j];
+    an[j] = xv[j];
+  }
   const int pf = ldc(a.pair_first, v), pm = ldc(a.pair_mid, v), pz = ldc(a.pair_first, v + 1);
-  const int lb = ldc(a.lrec_ptr, v);
-  const int nf = pm - pf, np = pz - pf;
-  flat_pairs<RPL, true>(a, xb, pf + max(u0, 0), pf + min(u1, nf), rc, xv, g, lsum, usum);
-  flat_pairs<RPL, false>(a, xb, pf + max(u0, nf), pf + min(u1, np), rc, xv, g, lsum, usum);
-  const int nl = ldc(a.lrec_ptr, v + 1) - lb;
-  flat_rows<RPL>(a, lb + max(u0 - np, 0), lb + min(u1 - np, nl), rc, xv, g);
+  const int lb = ldc(a.lrec_ptr, v), lm = ldc(a.lrec_mid, v), lz = ldc(a.lrec_ptr, v + 1);
+  const int nf = pm - pf, np = pz - pf, nl = lz - lb;
+  flat_pairs<RPL, true, PF>(a, xb, ldx4, rc4, pf + max(u0, 0), pf + min(u1, nf), ap, an, g, lsum,
+                            usum);
+  flat_pairs<RPL, false, PF>(a, xb, ldx4, rc4, pf + max(u0, nf), pf + min(u1, np), ap, an, g, lsum,
+                             usum);
+  flat_rows<RPL, PF>(a, qb, ldq4, rc4, lb + max(u0 - np, 0), lm, lb + min(u1 - np, nl), ap, an, g);
 }
 
 // Whole variables of the chunk's range: the gradient, then the epilogue.
-template <int LPI, int RPL, int MODE>
+template <int LPI, int RPL, int MODE, bool PF>
 __global__ __launch_bounds__(kBlock) void k_flat_var(VarPassArgs a) {
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
@@ -292,7 +378,8 @@ __global__ __launch_bounds__(kBlock) void k_flat_var(VarPassArgs a) {
   const bool active = r0 < a.R;
   const int rc = active ? r0 : 0;  // in-bounds column for lanes past the last restart
   const int vb = ldc(a.chunk_vbeg, chunk), ve = ldc(a.chunk_vend, chunk);
-  const float* xb = a.x + (int64_t)ldc(a.chunk_fvb, chunk) * a.ldx;
+  const char* xb = reinterpret_cast<const char*>(a.x + (int64_t)ldc(a.chunk_fvb, chunk) * a.ldx);
+  const char* qb = reinterpret_cast<const char*>(a.qrow + (int64_t)ldc(a.chunk_rbase, chunk) * a.ldq);
   double lsum[RPL];
   int usum[RPL];
 #pragma unroll
@@ -304,8 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_flat_var(VarPassArgs a) {
 #pragma unroll
     for (int j = 0; j < RPL; ++j) g[j] = 0.0;
     load_row<RPL>(a.x + (int64_t)v * a.ldx + rc, xv);
-    flat_range<RPL>(a, xb, v, 0, 0x7fffffff, rc, xv, g, lsum, usum);
-    if (active) var_epilogue<RPL, MODE>(a, v, r0, xv, g);
+    flat_range<RPL, PF>(a, xb, qb, v, 0, 0x7fffffff, rc, xv, g, lsum, usum);
+    if (active) var_epilogue<RPL, MODE, true>(a, v, r0, xv, g);
   }
   block_partials<LPI, RPL>(lsum, usum, a.chunk_row[chunk], tile, a.R, a.loss_part, a.unsat_part);
 }
@@ -313,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_flat_var(VarPassArgs a) {
 // Segments of split variables: each segment's partial gradient (its
 // unified range [seg_q0 - var_ptr[v], seg_q1 - var_ptr[v])) goes to
 // gseg[s][r] in FP64; k_heavy_finish adds them in segment order.
-template <int LPI, int RPL>
+template <int LPI, int RPL, bool PF>
 __global__ __launch_bounds__(kBlock) void k_flat_seg(VarPassArgs a) {
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
@@ -331,15 +418,17 @@ __global__ __launch_bounds__(kBlock) void k_flat_seg(VarPassArgs a) {
   for (int s0 = sb + slot; s0 < se; s0 += IPB) {
     const int sgi = uniform<LPI>(s0);
     const int v = ldc(a.seg_var, sgi);
-    const int qb = ldc(a.var_ptr, v);
-    const float* xb = a.x + (int64_t)ldc(a.f_vbeg, ldc(a.var_formula, v)) * a.ldx;
+    const int qv = ldc(a.var_ptr, v);
+    const int f = ldc(a.var_formula, v);
+    const char* xb = reinterpret_cast<const char*>(a.x + (int64_t)ldc(a.f_vbeg, f) * a.ldx);
+    const char* qb = reinterpret_cast<const char*>(a.qrow + (int64_t)ldc(a.f_rbeg, f) * a.ldq);
     double g[RPL];
     float xv[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; ++j) g[j] = 0.0;
     load_row<RPL>(a.x + (int64_t)v * a.ldx + rc, xv);
-    flat_range<RPL>(a, xb, v, ldc(a.seg_q0, sgi) - qb, ldc(a.seg_q1, sgi) - qb, rc, xv, g, lsum,
-                    usum);
+    flat_range<RPL, PF>(a, xb, qb, v, ldc(a.seg_q0, sgi) - qv, ldc(a.seg_q1, sgi) - qv, rc, xv, g,
+                        lsum, usum);
     if (active) {
 #pragma unroll
       for (int j = 0; j < RPL; ++j) a.gseg[(int64_t)sgi * a.R + r0 + j] = g[j];
@@ -352,15 +441,21 @@ __global__ __launch_bounds__(kBlock) void k_flat_seg(VarPassArgs a) {
 
 namespace {
 
-template <int LPI, int RPL>
-hipError_t flat_var_rpl(const VarPassArgs& a, int mode, int chunks, int tiles, hipStream_t s) {
+template <int LPI, int RPL, bool PF>
+hipError_t flat_var_pf(const VarPassArgs& a, int mode, int chunks, int tiles, hipStream_t s) {
   dim3 grid(chunks, tiles), block(kBlock);
   switch (mode) {
-    case kModeSGD: hipLaunchKernelGGL((k_flat_var<LPI, RPL, kModeSGD>), grid, block, 0, s, a); break;
-    case kModeAdam: hipLaunchKernelGGL((k_flat_var<LPI, RPL, kModeAdam>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_flat_var<LPI, RPL, kModeGrad>), grid, block, 0, s, a); break;
+    case kModeSGD: hipLaunchKernelGGL((k_flat_var<LPI, RPL, kModeSGD, PF>), grid, block, 0, s, a); break;
+    case kModeAdam: hipLaunchKernelGGL((k_flat_var<LPI, RPL, kModeAdam, PF>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_flat_var<LPI, RPL, kModeGrad, PF>), grid, block, 0, s, a); break;
   }
   return hipGetLastError();
+}
+
+template <int LPI, int RPL>
+hipError_t flat_var_rpl(const VarPassArgs& a, int mode, int chunks, int tiles, hipStream_t s) {
+  return a.prefetch ? flat_var_pf<LPI, RPL, true>(a, mode, chunks, tiles, s)
+                    : flat_var_pf<LPI, RPL, false>(a, mode, chunks, tiles, s);
 }
 
 template <int LPI>
@@ -376,10 +471,18 @@ hipError_t flat_var_lpi(const VarPassArgs& a, int mode, Tile t, int chunks, int 
 template <int LPI>
 hipError_t flat_seg_lpi(const VarPassArgs& a, Tile t, int chunks, int tiles, hipStream_t s) {
   dim3 grid(chunks, tiles), block(kBlock);
-  switch (t.rpl) {
-    case 4: hipLaunchKernelGGL((k_flat_seg<LPI, 4>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_flat_seg<LPI, 2>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_flat_seg<LPI, 1>), grid, block, 0, s, a); break;
+  if (a.prefetch) {
+    switch (t.rpl) {
+      case 4: hipLaunchKernelGGL((k_flat_seg<LPI, 4, true>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_flat_seg<LPI, 2, true>), grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_flat_seg<LPI, 1, true>), grid, block, 0, s, a); break;
+    }
+  } else {
+    switch (t.rpl) {
+      case 4: hipLaunchKernelGGL((k_flat_seg<LPI, 4, false>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_flat_seg<LPI, 2, false>), grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_flat_seg<LPI, 1, false>), grid, block, 0, s, a); break;
+    }
   }
   return hipGetLastError();
 }

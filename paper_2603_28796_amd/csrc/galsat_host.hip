@@ -43,6 +43,7 @@ constexpr int64_t kCacheBudgetBytes = 256ll << 20;  // state rows one launch may
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 constexpr int64_t kXcdChunks = 160;                 // workgroups resident on one XCD (about)
 constexpr int64_t kXcdChunksTwoPhase = 20;          // measured for the two-phase passes
+constexpr int64_t kXcdChunksFlat = 40;              // measured for the flat plan (batch of 4,096)
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -138,6 +139,7 @@ struct galsat_ctx {
   int xcd_pin = 0;       // single pass: restart tiles mapped to XCDs
   int two_phase = 0;     // occurrence pass + variable sum instead of the single pass
   int flat = 0;          // flat plan: pair records + clause rows (galsat_flat.hip)
+  int prefetch = 1;      // flat plan: next batch's records loaded during this batch's gathers
   int32_t xseq = 0;      // chunks of the XCD-contiguous order (0: off)
   int lds_rg = 0;        // restart group of the persistent LDS schedule (0: not used)
   int lds_stage = 0;     // its occurrence records staged in LDS
@@ -185,13 +187,16 @@ struct galsat_ctx {
   int32_t *ach_beg = nullptr, *ach_end = nullptr;
   // flat plan
   int2* pairs = nullptr;
-  int32_t *pair_first = nullptr, *pair_mid = nullptr, *lrec_ptr = nullptr;
+  int32_t *pair_first = nullptr, *pair_fneg = nullptr, *pair_mid = nullptr, *lrec_ptr = nullptr,
+          *lrec_mid = nullptr;
   uint32_t* lrec = nullptr;
   uint32_t* qrow = nullptr;  // [clause rows][ld] packed per-clause products
   int32_t *row_ids = nullptr, *rch_beg = nullptr, *rch_end = nullptr, *rch_row = nullptr;
   int32_t* rch_order = nullptr;
   int32_t n_rorder = 0;
   int32_t* vch_fvb = nullptr;  // [variable chunks] first variable of the chunk's formula
+  int32_t* vch_rbase = nullptr;  // [variable chunks] first clause row of the chunk's formula
+  int32_t* f_rbeg = nullptr;     // [F+1] first clause row of each formula
   int32_t *seg_var = nullptr, *seg_q0 = nullptr, *seg_q1 = nullptr;
   int32_t *heavy_var = nullptr, *heavy_sbeg = nullptr;
   int32_t *fin_step_a0 = nullptr, *fin_step_a1 = nullptr;
@@ -396,12 +401,14 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // ldsrg (restarts per workgroup of the LDS schedule: 1, 2, 4, 8, 16 or 32)
 // ldsstage (0: the LDS schedule reads records from global memory), ldslpt
 // (0: the LDS schedule issues formulas in index order), xpin (1/0: the
-// single pass maps restart tiles to XCDs or not) and flat (1/0: the flat
-// plan of pair records and clause rows, or not).
+// single pass maps restart tiles to XCDs or not), flat (1/0: the flat plan
+// of pair records and clause rows, or not), pf (flat plan: 1/0, records of
+// the next batch prefetched or not) and rsort (flat plan: 1/0, a variable's
+// clause rows in row order or in slot order).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
                     int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
                     int* short_clauses, int* xseq, int* segdiv, int* ldsrg, int* ldsstage,
-                    int* ldslpt, int* xpin, int* flat) {
+                    int* ldslpt, int* xpin, int* flat, int* pf, int* rsort) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -431,6 +438,8 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "ldslpt") *ldslpt = v;
       else if (k == "xpin") *xpin = v;
       else if (k == "flat") *flat = v;
+      else if (k == "pf") *pf = v;
+      else if (k == "rsort") *rsort = v;
     }
     pos = comma + 1;
   }
@@ -613,10 +622,10 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // ---- plan: which clauses recompute their partials in the variable pass
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
   int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1, segdiv_o = -1;
-  int ldsrg_o = 0, ldsstage_o = -1, ldslpt_o = -1, xpin_o = -1, flat_o = -1;
+  int ldsrg_o = 0, ldsstage_o = -1, ldslpt_o = -1, xpin_o = -1, flat_o = -1, pf_o = -1, rsort_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
                  &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o, &ldsrg_o, &ldsstage_o,
-                 &ldslpt_o, &xpin_o, &flat_o);
+                 &ldslpt_o, &xpin_o, &flat_o, &pf_o, &rsort_o);
   const bool csort = csort_o != 0;
   // Persistent LDS schedule: every formula's restart group must fit in LDS
   // (state double-buffered); SGD only; every clause recomputed.
@@ -695,8 +704,17 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   {
     const bool krec_set = opt.recompute_max_len > 0 ||
                           (opt.plan_override && std::strstr(opt.plan_override, "krec="));
+    // the variable pass addresses a formula's state rows and clause rows by
+    // 32-bit byte offsets and its local indices by 24-bit multiplies
     bool fit = !h->stream_items && !lds_rg && opt.partials != GALSAT_PARTIALS_RECOMPUTE;
-    for (int32_t f = 0; f < F && fit; ++f) fit = fvb[f + 1] - fvb[f] < (1 << 30);
+    const int64_t row_bytes = round_up(R, 4) * 4;
+    for (int32_t f = 0; f < F && fit; ++f) {
+      int64_t rows_f = 0;
+      for (int32_t t = fcb[f]; t < fcb[f + 1]; ++t) rows_f += (cp[t + 1] - cp[t] != 3 && cp[t + 1] > cp[t]) ? 1 : 0;
+      const int64_t nf = fvb[f + 1] - fvb[f];
+      fit = nf < (1 << 24) && rows_f < (1 << 24) && nf * row_bytes < (int64_t(1) << 32) &&
+            rows_f * row_bytes < (int64_t(1) << 32);
+    }
     if (fit && opt.workspace_budget_bytes > 0) {
       int64_t rows = 0;
       for (int32_t t = 0; t < m; ++t) rows += (cp[t + 1] - cp[t] != 3 && cp[t + 1] > cp[t]) ? 1 : 0;
@@ -709,7 +727,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   }
   // chunks per formula of the XCD-aware order (several formulas per launch)
   const int64_t xcd_chunks =
-      xcdc_o >= 0 ? xcdc_o : (h->two_phase ? kXcdChunksTwoPhase : kXcdChunks);
+      xcdc_o >= 0 ? xcdc_o
+                  : (h->two_phase ? kXcdChunksTwoPhase : h->flat ? kXcdChunksFlat : kXcdChunks);
   h->tile = choose_tile(R, 4);
   if ((h->two_phase || h->flat) && R % 4 == 0 && R >= 16) {
     // four restarts per lane measured faster for the two-phase passes (and
@@ -852,10 +871,15 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // variable, in variable-major slot order: pair records of the 3-literal
   // clauses whose first literal is the variable's own occurrence, then the
   // other pair records, then clause-row records.
-  std::vector<int32_t> row_ids, row_of, pair_first, pair_mid, lrec_ptr;
+  std::vector<int32_t> row_ids, row_of, pair_first, pair_fneg, pair_mid, lrec_ptr, lrec_mid;
   std::vector<int64_t> f_rbeg((size_t)F + 1, 0);
   std::vector<int2> pairs;
   std::vector<uint32_t> lrec;
+  const bool rsort = rsort_o != 0;
+  // Prefetching the next batch's records pays when a variable's record runs
+  // span several batches (measured: +7 % at 38 occurrences per variable,
+  // -13 % at 14), so by default from 24 occurrences per variable on.
+  h->prefetch = pf_o >= 0 ? (pf_o ? 1 : 0) : ((int64_t)L >= 24 * (int64_t)std::max(n, 1) ? 1 : 0);
   if (flat) {
     row_of.assign((size_t)std::max(m, 1), -1);
     for (int32_t f = 0; f < F; ++f) {
@@ -870,15 +894,17 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     }
     f_rbeg[F] = (int64_t)row_ids.size();
     for (size_t i = 0; i < row_ids.size(); ++i) row_of[row_ids[i]] = (int32_t)i;
-    std::vector<int64_t> np((size_t)n + 1, 0), nr((size_t)n + 1, 0), nf((size_t)n, 0);
+    std::vector<int64_t> np((size_t)n + 1, 0), nr((size_t)n + 1, 0), nf((size_t)n, 0),
+        nfp((size_t)n, 0);
     parallel_for(n, [&](int64_t v0, int64_t v1) {
       for (int64_t v = v0; v < v1; ++v) {
-        int64_t a3 = 0, fst = 0, b = 0;
+        int64_t a3 = 0, fst = 0, fpos = 0, b = 0;
         for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
           const int32_t p = vo[q], t = clause_of[p];
           if (cp[t + 1] - cp[t] == 3) {
             ++a3;
             fst += p == cp[t] ? 1 : 0;
+            fpos += (p == cp[t] && (cl[p] & 1) == 0) ? 1 : 0;
           } else {
             ++b;
           }
@@ -886,6 +912,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
         np[v + 1] = a3;
         nr[v + 1] = b;
         nf[v] = fst;
+        nfp[v] = fpos;
       }
     });
     for (int32_t v = 0; v < n; ++v) {
@@ -894,11 +921,16 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     }
     pair_first.resize((size_t)n + 1);
     pair_mid.resize((size_t)std::max(n, 1));
+    lrec_mid.assign((size_t)std::max(n, 1), 0);
     lrec_ptr.resize((size_t)n + 1);
+    pair_fneg.resize((size_t)std::max(n, 1));
     for (int32_t v = 0; v <= n; ++v) {
       pair_first[v] = (int32_t)np[v];
       lrec_ptr[v] = (int32_t)nr[v];
-      if (v < n) pair_mid[v] = (int32_t)(np[v] + nf[v]);
+      if (v < n) {
+        pair_fneg[v] = (int32_t)(np[v] + nfp[v]);
+        pair_mid[v] = (int32_t)(np[v] + nf[v]);
+      }
     }
     pairs.resize((size_t)std::max<int64_t>(np[n], 1));
     lrec.resize((size_t)std::max<int64_t>(nr[n], 1));
@@ -906,7 +938,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       for (int64_t vv = v0; vv < v1; ++vv) {
         const int32_t v = (int32_t)vv;
         const int32_t base2 = 2 * fvb[var_formula[v]];
-        int64_t af = pair_first[v], ao = pair_mid[v], b = lrec_ptr[v];
+        int64_t af = pair_first[v], an = pair_fneg[v], ao = pair_mid[v], b = lrec_ptr[v];
         for (int32_t q = vp[v]; q < vp[v + 1]; ++q) {
           const int32_t p = vo[q], t = clause_of[p];
           const uint32_t own_neg = (uint32_t)(cl[p] & 1) << 31;
@@ -915,12 +947,28 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
             for (int32_t i = cp[t]; i < cp[t + 1]; ++i)
               if (i != p) o[c++] = cl[i] - base2;
             const int2 rec = make_int2((int32_t)((uint32_t)o[0] | own_neg), o[1]);
-            if (p == cp[t]) pairs[(size_t)af++] = rec;
+            if (p == cp[t] && !own_neg) pairs[(size_t)af++] = rec;
+            else if (p == cp[t]) pairs[(size_t)an++] = rec;
             else pairs[(size_t)ao++] = rec;
           } else {
-            lrec[(size_t)b++] = (uint32_t)row_of[t] | own_neg;
+            lrec[(size_t)b++] = (uint32_t)(row_of[t] - f_rbeg[var_formula[v]]) | own_neg;
           }
         }
+        // a variable's clause rows: positive own literals first, then
+        // negated ones (one partial sign per run), each in row order, so a
+        // hot variable, which meets most long clauses, sweeps the rows
+        // nearly sequentially; the sign bit is then dropped
+        if (rsort)
+          std::sort(lrec.begin() + lrec_ptr[v], lrec.begin() + b, [](uint32_t p1, uint32_t p2) {
+            return (p1 >> 31) < (p2 >> 31) || ((p1 >> 31) == (p2 >> 31) && p1 < p2);
+          });
+        else
+          std::stable_sort(lrec.begin() + lrec_ptr[v], lrec.begin() + b,
+                           [](uint32_t p1, uint32_t p2) { return (p1 >> 31) < (p2 >> 31); });
+        int64_t mid = lrec_ptr[v];
+        while (mid < b && (lrec[(size_t)mid] >> 31) == 0) ++mid;
+        lrec_mid[v] = (int32_t)mid;
+        for (int64_t i = lrec_ptr[v]; i < b; ++i) lrec[(size_t)i] &= 0x7fffffffu;
       }
     });
   }
@@ -1087,14 +1135,18 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
         }
       }
       if (fvb[f + 1] > cb) { vc.beg.push_back(cb); vc.end.push_back(fvb[f + 1]); }
-      // segment chunks of this formula: about `target` cost each
+      // segment chunks of this formula: about one segment per item slot in
+      // the flat plan, so no slot walks several segments in a row and the
+      // hottest variables spread over the chip; about `target` cost each
+      // otherwise
       sc.f_first[f] = sc.count();
       const int32_t s_lo = heavy_sbeg[heavy_f_first[f]], s_hi = (int32_t)seg_var.size();
       int32_t sb = s_lo;
       int64_t sacc = 0;
+      const int64_t seg_target = flat ? std::max<int64_t>(64, seg_cap * ipb) : target_f;
       for (int32_t sg = s_lo; sg < s_hi; ++sg) {
         for (int32_t q = seg_q0[sg]; q < seg_q1[sg]; ++q) sacc += occ_cost[q];
-        if (sacc >= target_f || sg + 1 == s_hi) {
+        if (sacc >= seg_target || sg + 1 == s_hi) {
           sc.beg.push_back(sb);
           sc.end.push_back(sg + 1);
           sb = sg + 1;
@@ -1430,9 +1482,11 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   if (flat) {
     UP(pairs, pairs);
     UP(pair_first, pair_first);
+    UP(pair_fneg, pair_fneg);
     UP(pair_mid, pair_mid);
     UP(lrec, lrec);
     UP(lrec_ptr, lrec_ptr);
+    UP(lrec_mid, lrec_mid);
     UP(row_ids, row_ids);
     UP(rch_beg, c->rch.beg);
     UP(rch_end, c->rch.end);
@@ -1443,6 +1497,12 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     for (int32_t f = 0; f < F; ++f)
       for (int ch = c->vch.f_first[f]; ch < c->vch.f_first[f + 1]; ++ch) vfvb[ch] = fvb[f];
     UP(vch_fvb, vfvb);
+    std::vector<int32_t> vrb((size_t)std::max(VC, 1), 0), frb((size_t)F + 1);
+    for (int32_t f = 0; f < F; ++f)
+      for (int ch = c->vch.f_first[f]; ch < c->vch.f_first[f + 1]; ++ch) vrb[ch] = (int32_t)f_rbeg[f];
+    for (int32_t f = 0; f <= F; ++f) frb[f] = (int32_t)f_rbeg[f];
+    UP(vch_rbase, vrb);
+    UP(f_rbeg, frb);
     AL(qrow, (size_t)std::max<size_t>(row_ids.size(), 1) * (size_t)c->ld);
   }
   UP(segch_beg, c->segch.beg);
@@ -1596,13 +1656,18 @@ VarPassArgs var_args(const galsat_ctx* h) {
   a.ldD = h->ldD;
   a.pairs = h->pairs;
   a.pair_first = h->pair_first;
+  a.pair_fneg = h->pair_fneg;
   a.pair_mid = h->pair_mid;
   a.lrec = h->lrec;
   a.lrec_ptr = h->lrec_ptr;
+  a.lrec_mid = h->lrec_mid;
+  a.prefetch = h->prefetch;
   a.qrow = h->qrow;
   a.ldq = h->ld;
   a.chunk_fvb = h->vch_fvb;
+  a.chunk_rbase = h->vch_rbase;
   a.f_vbeg = h->f_vbeg;
+  a.f_rbeg = h->f_rbeg;
   a.loss_part = h->loss_part;
   a.unsat_part = h->unsat_part;
   a.R = h->R;
@@ -1676,6 +1741,9 @@ galsat_status two_phase_passes(galsat_ctx* h, VarPassArgs va, Tile t, int mode, 
 galsat_status flat_passes(galsat_ctx* h, VarPassArgs va, Tile t, int mode, int f0, int f1,
                           hipStream_t s) {
   const bool all = f0 == 0 && f1 == h->F;
+  // state rows are addressed by 32-bit byte offsets within a formula
+  if ((int64_t)h->nf_max * va.ldx * 4 >= (int64_t(1) << 32))
+    return h->fail(GALSAT_EUNSUPPORTED, "flat plan: a formula's state at this row stride exceeds 4 GiB");
   const int rc0 = h->rch.f_first[f0], rc1 = h->rch.f_first[f1];
   if (rc1 > rc0) {
     ClausePassArgs ca{};

@@ -87,46 +87,16 @@ bool plan_cache_lookup(const std::string& key, std::string* plan) {
 
 }  // namespace galsat
 
-extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsat_options* opt_in,
-                                         const float* x0, int32_t ldx, int32_t steps, void* stream,
-                                         char* plan_out, int32_t plan_cap, double* best_ms) {
-  if (!prob || !x0 || ldx < prob->restarts || steps < 1 || !plan_out || plan_cap < 64)
-    return GALSAT_EINVAL;
-  galsat_options base;
-  if (opt_in) base = *opt_in; else galsat_default_options(&base);
-  base.use_graph = 0;
-  const int R = prob->restarts, n = prob->n_vars;
-  std::vector<int32_t> len;
-  if (!clause_lengths(prob, &len)) return GALSAT_EDEVICE;
-  int kmax = 0;
-  int64_t long_lits = 0;
-  for (int32_t k : len) {
-    kmax = std::max(kmax, k);
-    if (k > 8) long_lits += k;
-  }
-  // tiles: wide restart batches favour 4 restarts per lane, small ones one
-  std::vector<std::string> tiles;
-  if (R > 32) {
-    tiles = {"lpi=64,rpl=4"};
-    if (R % 2 == 0) tiles.push_back("lpi=64,rpl=2");
-    if (R >= 128) tiles.push_back("lpi=32,rpl=4");
-  } else {
-    const int p = std::max(4, std::min(64, pow2_at_least(R)));
-    tiles = {"lpi=" + std::to_string(p) + ",rpl=1"};
-    if (p != 64) tiles.push_back("lpi=64,rpl=1");
-    if (R % 4 == 0 && p / 4 >= 4) tiles.push_back("lpi=" + std::to_string(p / 4) + ",rpl=4");
-  }
-  // recompute threshold from the clause-length histogram: with long clauses
-  // present, storing their partials competes with recomputing them
-  std::vector<std::string> krecs = {""};
-  if (base.partials == GALSAT_PARTIALS_AUTO && kmax > 8 && long_lits > 0)
-    krecs = {",krec=8", ",krec=" + std::to_string(kmax)};
-  std::vector<std::string> xcd = {""};
-  if (prob->num_formulas > 1 && base.schedule != GALSAT_SCHED_PLAIN) xcd = {"", ",xcdc=160", ",xcdc=20"};
-  // narrow restart batches: the single pass against the two-phase gradient
-  std::vector<std::string> twos = {""};
-  if (R <= 64) twos = {",two=0", ",two=1"};
+namespace galsat {
 
+// Times each candidate plan on `steps` real steps from x0 (after one warm-up
+// step) and keeps the fastest; candidates that do not fit the workspace are
+// skipped.
+galsat_status tune_plans(const galsat_problem* prob, const galsat_options& base, const float* x0,
+                         int32_t ldx, int32_t steps, void* stream,
+                         const std::vector<std::string>& plans, char* plan_out, int32_t plan_cap,
+                         double* best_ms) {
+  const int n = prob->n_vars;
   hipStream_t s = static_cast<hipStream_t>(stream);
   float* xs = nullptr;
   if (hipMalloc(&xs, (size_t)std::max(n, 1) * ldx * sizeof(float)) != hipSuccess) return GALSAT_ENOMEM;
@@ -144,18 +114,6 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
   double best = 1e300;
   std::string best_plan;
   galsat_status result = GALSAT_OK;
-  std::vector<std::string> plans;
-  for (const auto& t : tiles)
-    for (const auto& k : krecs)
-      for (const auto& x : xcd)
-        for (const auto& w : twos) plans.push_back(t + k + x + w);
-  if (base.schedule == GALSAT_SCHED_LDS) {
-    // the persistent schedule has its own choices: restarts per workgroup
-    // (up to the restarts rounded to a power of two) and record staging
-    plans.clear();
-    for (int g = 1; g <= 32 && g < 2 * R; g *= 2)
-      for (const char* st : {"", ",ldsstage=0"}) plans.push_back("ldsrg=" + std::to_string(g) + st);
-  }
   for (const auto& plan : plans) {
     galsat_options o = base;
     o.plan_override = plan.c_str();
@@ -200,4 +158,75 @@ extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsa
     }
   }
   return GALSAT_OK;
+}
+
+}  // namespace galsat
+
+extern "C" galsat_status galsat_autotune(const galsat_problem* prob, const galsat_options* opt_in,
+                                         const float* x0, int32_t ldx, int32_t steps, void* stream,
+                                         char* plan_out, int32_t plan_cap, double* best_ms) {
+  if (!prob || !x0 || ldx < prob->restarts || steps < 1 || !plan_out || plan_cap < 64)
+    return GALSAT_EINVAL;
+  galsat_options base;
+  if (opt_in) base = *opt_in; else galsat_default_options(&base);
+  base.use_graph = 0;
+  const int R = prob->restarts;
+  std::vector<int32_t> len;
+  if (!clause_lengths(prob, &len)) return GALSAT_EDEVICE;
+  int kmax = 0;
+  int64_t long_lits = 0;
+  for (int32_t k : len) {
+    kmax = std::max(kmax, k);
+    if (k > 8) long_lits += k;
+  }
+  // Narrow restart batches with AUTO partials run the flat plan: the
+  // candidates are both record-prefetch choices (one of them the plan's own
+  // choice), other chunk counts per formula for batches, and the two-phase
+  // plan.
+  if (R <= 64 && base.partials == GALSAT_PARTIALS_AUTO && base.schedule != GALSAT_SCHED_LDS &&
+      base.recompute_max_len == 0) {
+    std::vector<std::string> plans = {"flat=1,pf=0", "flat=1,pf=1"};
+    if (prob->num_formulas > 1 && base.schedule != GALSAT_SCHED_PLAIN) {
+      plans.push_back("flat=1,xcdc=20");
+      plans.push_back("flat=1,xcdc=80");
+    }
+    plans.push_back("two=1");
+    return galsat::tune_plans(prob, base, x0, ldx, steps, stream, plans, plan_out, plan_cap, best_ms);
+  }
+  // tiles: wide restart batches favour 4 restarts per lane, small ones one
+  std::vector<std::string> tiles;
+  if (R > 32) {
+    tiles = {"lpi=64,rpl=4"};
+    if (R % 2 == 0) tiles.push_back("lpi=64,rpl=2");
+    if (R >= 128) tiles.push_back("lpi=32,rpl=4");
+  } else {
+    const int p = std::max(4, std::min(64, pow2_at_least(R)));
+    tiles = {"lpi=" + std::to_string(p) + ",rpl=1"};
+    if (p != 64) tiles.push_back("lpi=64,rpl=1");
+    if (R % 4 == 0 && p / 4 >= 4) tiles.push_back("lpi=" + std::to_string(p / 4) + ",rpl=4");
+  }
+  // recompute threshold from the clause-length histogram: with long clauses
+  // present, storing their partials competes with recomputing them
+  std::vector<std::string> krecs = {""};
+  if (base.partials == GALSAT_PARTIALS_AUTO && kmax > 8 && long_lits > 0)
+    krecs = {",krec=8", ",krec=" + std::to_string(kmax)};
+  std::vector<std::string> xcd = {""};
+  if (prob->num_formulas > 1 && base.schedule != GALSAT_SCHED_PLAIN) xcd = {"", ",xcdc=160", ",xcdc=20"};
+  // narrow restart batches: the single pass against the two-phase gradient
+  std::vector<std::string> twos = {""};
+  if (R <= 64) twos = {",two=0", ",two=1"};
+
+  std::vector<std::string> plans;
+  for (const auto& t : tiles)
+    for (const auto& k : krecs)
+      for (const auto& x : xcd)
+        for (const auto& w : twos) plans.push_back(t + k + x + w);
+  if (base.schedule == GALSAT_SCHED_LDS) {
+    // the persistent schedule has its own choices: restarts per workgroup
+    // (up to the restarts rounded to a power of two) and record staging
+    plans.clear();
+    for (int g = 1; g <= 32 && g < 2 * R; g *= 2)
+      for (const char* st : {"", ",ldsstage=0"}) plans.push_back("ldsrg=" + std::to_string(g) + st);
+  }
+  return galsat::tune_plans(prob, base, x0, ldx, steps, stream, plans, plan_out, plan_cap, best_ms);
 }
