@@ -57,10 +57,6 @@ __device__ __forceinline__ uint32_t clause_pack(double q, int zeros) {
   return (uint32_t)(b >> 33) | (zeros == 1 ? 0x80000000u : 0u);
 }
 
-__device__ __forceinline__ double clause_value(uint32_t u) {
-  return __longlong_as_double((long long)((uint64_t)(u & 0x7fffffffu) << 33));
-}
-
 template <int N>
 __device__ __forceinline__ void load_urow(const uint32_t* __restrict__ p, uint32_t (&o)[N]) {
   if constexpr (N == 4) {

@@ -122,14 +122,32 @@ __global__ __launch_bounds__(256) void k_confidence(const float* d, int32_t ldd,
 // f in candidate k, ties to the lower index, written in increasing index
 // order.  Keys are 64-bit: confidence bits (inverted for LOW) above the
 // inverted local index, so every key is distinct and larger = preferred.
-// An exact radix select (eight 8-bit digits, integer counts in LDS) finds
-// the S-th largest key; a block scan then compacts the selected indices.
+// An exact radix select (8-bit digits from the top, integer counts in LDS)
+// finds the S-th largest key; a block scan then compacts the selected
+// indices.
 template <bool HIGH>
 __device__ __forceinline__ uint64_t sel_key(float c, int local) {
   const uint32_t b = __float_as_uint(c);
   const uint64_t hi = HIGH ? b : ~b;
   return (hi << 32) | (uint64_t)(~(uint32_t)local);
 }
+
+// Adds one to hist[bin] for every active lane.  Confidences share their top
+// key bytes, so most lanes of a wave usually name the same bin: the lanes
+// that share the first active lane's bin add their count with one atomic,
+// the rest add one each.
+__device__ __forceinline__ void hist_add(uint32_t* hist, bool act, uint32_t bin) {
+  const uint64_t am = __ballot(act);
+  if (am == 0) return;
+  const int lead = __builtin_ctzll(am);
+  const uint32_t lb = (uint32_t)__shfl((int)bin, lead, 64);
+  const bool same = act && bin == lb;
+  const uint64_t sm = __ballot(same);
+  if ((int)(threadIdx.x & 63) == lead) atomicAdd(&hist[lb], (uint32_t)__popcll(sm));
+  if (act && !same) atomicAdd(&hist[bin], 1u);
+}
+
+constexpr int kSelU = 8;  // confidence loads in flight per thread
 
 template <bool HIGH>
 __global__ __launch_bounds__(1024) void k_select(const float* conf, int32_t n,
@@ -142,11 +160,12 @@ __global__ __launch_bounds__(1024) void k_select(const float* conf, int32_t n,
   const float* c = conf + (int64_t)k * n + v0;
   __shared__ uint32_t hist[256];
   __shared__ uint64_t s_prefix, s_mask;
-  __shared__ int s_rank;
+  __shared__ int s_rank, s_done;
   if (tid == 0) {
     s_prefix = 0;
     s_mask = 0;
     s_rank = S;
+    s_done = 0;
   }
   __syncthreads();
   for (int pass = 0; pass < 8; ++pass) {
@@ -154,9 +173,21 @@ __global__ __launch_bounds__(1024) void k_select(const float* conf, int32_t n,
     for (int b = tid; b < 256; b += nt) hist[b] = 0;
     __syncthreads();
     const uint64_t prefix = s_prefix, mask = s_mask;
-    for (int i = tid; i < nf; i += nt) {
-      const uint64_t key = sel_key<HIGH>(c[i], i);
-      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1u);
+    // kSelU block strides per iteration, all their loads issued first; the
+    // loop runs the same count on every lane, so the ballots see whole waves
+    for (int base = 0; base < nf; base += nt * kSelU) {
+      float cv[kSelU];
+#pragma unroll
+      for (int u = 0; u < kSelU; ++u) {
+        const int i = base + u * nt + tid;
+        cv[u] = i < nf ? c[i] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kSelU; ++u) {
+        const int i = base + u * nt + tid;
+        const uint64_t key = sel_key<HIGH>(cv[u], i);
+        hist_add(hist, i < nf && (key & mask) == prefix, (uint32_t)(key >> shift) & 255u);
+      }
     }
     __syncthreads();
     if (tid == 0) {
@@ -172,30 +203,49 @@ __global__ __launch_bounds__(1024) void k_select(const float* conf, int32_t n,
       s_prefix = prefix | ((uint64_t)chosen << shift);
       s_mask = mask | (0xFFULL << shift);
       s_rank = rank;
+      // every key under the new prefix is selected: keys >= the prefix with
+      // zero lower digits are exactly the selection
+      s_done = (int)hist[chosen] == rank;
     }
     __syncthreads();
+    if (s_done) break;
   }
-  const uint64_t thr = s_prefix;  // the S-th largest key: keys >= thr are the selection
-  __shared__ int cnt[1024];
+  const uint64_t thr = s_prefix;  // keys >= thr are the selection
+  // exclusive scan of the per-thread counts: within each wave by shuffles,
+  // then over the wave totals
+  __shared__ int wave_tot[16];
   const int per = (nf + nt - 1) / nt;
   const int i0 = tid * per, i1 = min(nf, i0 + per);
+  // each thread's contiguous run, kSelU loads in flight (indices clamped
+  // into the run, the extra entries not counted)
   int mine = 0;
-  for (int i = i0; i < i1; ++i) mine += sel_key<HIGH>(c[i], i) >= thr ? 1 : 0;
-  cnt[tid] = mine;
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int t = 0; t < nt; ++t) {
-      const int x = cnt[t];
-      cnt[t] = acc;
-      acc += x;
-    }
+  for (int i = i0; i < i1; i += kSelU) {
+    float cv[kSelU];
+#pragma unroll
+    for (int u = 0; u < kSelU; ++u) cv[u] = c[min(i + u, i1 - 1)];
+#pragma unroll
+    for (int u = 0; u < kSelU; ++u) mine += (i + u < i1 && sel_key<HIGH>(cv[u], i + u) >= thr) ? 1 : 0;
   }
+  const int lane = tid & 63, w = tid >> 6;
+  int incl = mine;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wave_tot[w] = incl;
   __syncthreads();
-  int pos = cnt[tid];
+  int pos = incl - mine;
+  for (int u = 0; u < w; ++u) pos += wave_tot[u];
   int32_t* o = out + (int64_t)k * stot + sel_off[f];
-  for (int i = i0; i < i1; ++i)
-    if (sel_key<HIGH>(c[i], i) >= thr) o[pos++] = v0 + i;
+  for (int i = i0; i < i1; i += kSelU) {
+    float cv[kSelU];
+#pragma unroll
+    for (int u = 0; u < kSelU; ++u) cv[u] = c[min(i + u, i1 - 1)];
+#pragma unroll
+    for (int u = 0; u < kSelU; ++u)
+      if (i + u < i1 && sel_key<HIGH>(cv[u], i + u) >= thr) o[pos++] = v0 + i + u;
+  }
 }
 
 // ------------------------------------------------------------ launchers

@@ -297,9 +297,12 @@ __global__ __launch_bounds__(kBlock) void k_var_stream(VarPassArgs a) {
 
 // Segments of split variables (variables with more occurrences than one
 // item should serialise): each segment's partial gradient goes to
-// gseg[s][r] in FP64.
+// gseg[s][r] in FP64.  With one item per wave the segment walks are
+// latency-bound chains of gathers, and six waves per SIMD (a few spilled
+// registers) beat five without spills.
 template <int LPI, int RPL>
-__global__ __launch_bounds__(kBlock) void k_var_seg(VarPassArgs a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(LPI == 64 ? 6 : 1))) void k_var_seg(VarPassArgs a) {
   constexpr int IPB = kBlock / LPI;
   constexpr int RT = LPI * RPL;
   const int lane = threadIdx.x % LPI, slot = threadIdx.x / LPI;

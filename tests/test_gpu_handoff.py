@@ -75,3 +75,28 @@ def test_selection_with_many_ties_and_large_formula():
         for k in range(3):
             want = H.select(c[k], int(off[1]), highest=highest)
             assert np.array_equal(ids[k].cpu().numpy(), want)
+
+
+def test_selection_counts_from_one_to_all():
+    """Selections of 1, most and all variables of each formula, on distinct
+    confidences (the radix select stops once a digit's bin holds exactly the
+    remaining count) and on all-equal ones (every choice falls to the index
+    digits)."""
+    say("[handoff] counts 1..all")
+    cnf = _batch()
+    prob = Problem(cnf, 4)
+    rng = np.random.default_rng(47)
+    distinct = rng.uniform(0.5, 1.0, size=(2, cnf.n)).astype(np.float32)
+    equal = np.full((2, cnf.n), 0.75, dtype=np.float32)
+    for vals in (distinct, equal):
+        conf = torch.tensor(vals, device="cuda")
+        for highest, frac, mc in ((True, 0.0, 1), (False, 0.9, 1), (True, 1.0, 1), (False, 1.0, 0)):
+            off, ids = prob.select_vars(conf, highest=highest, frac=frac, min_count=mc)
+            torch.cuda.synchronize()
+            for f in range(cnf.F):
+                v0, v1 = cnf.formula_var_begin[f], cnf.formula_var_begin[f + 1]
+                cnt = H.select_count(v1 - v0, frac, mc)
+                assert off[f + 1] - off[f] == cnt
+                for k in range(2):
+                    want = v0 + H.select(vals[k, v0:v1], cnt, highest=highest)
+                    assert np.array_equal(ids[k, off[f]:off[f + 1]].cpu().numpy(), want), (f, k, frac)
