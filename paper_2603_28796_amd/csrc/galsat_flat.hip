@@ -350,8 +350,8 @@ __device__ __forceinline__ void flat_range(const VarPassArgs& a, const char* xb,
     ap[j] = 1.0f - xv[j];
     an[j] = xv[j];
   }
-  const int pf = ldc(a.pair_first, v), pm = ldc(a.pair_mid, v), pz = ldc(a.pair_first, v + 1);
-  const int lb = ldc(a.lrec_ptr, v), lm = ldc(a.lrec_mid, v), lz = ldc(a.lrec_ptr, v + 1);
+  const int pf = ldc(a.pair_first, v), pm = ldc(a.pair_mid, v), pz = ldc(a.pair_end, v);
+  const int lb = ldc(a.lrec_ptr, v), lm = ldc(a.lrec_mid, v), lz = ldc(a.lrec_end, v);
   const int nf = pm - pf, np = pz - pf, nl = lz - lb;
   flat_pairs<RPL, true, PF>(a, xb, ldx4, rc4, pf + max(u0, 0), pf + min(u1, nf), ap, an, g, lsum,
                             usum);

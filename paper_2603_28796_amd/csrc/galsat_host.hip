@@ -187,8 +187,8 @@ struct galsat_ctx {
   int32_t *ach_beg = nullptr, *ach_end = nullptr;
   // flat plan
   int2* pairs = nullptr;
-  int32_t *pair_first = nullptr, *pair_fneg = nullptr, *pair_mid = nullptr, *lrec_ptr = nullptr,
-          *lrec_mid = nullptr;
+  int32_t *pair_first = nullptr, *pair_end = nullptr, *pair_mid = nullptr, *lrec_ptr = nullptr,
+          *lrec_mid = nullptr, *lrec_end = nullptr;
   uint32_t* lrec = nullptr;
   uint32_t* qrow = nullptr;  // [clause rows][ld] packed per-clause products
   int32_t *row_ids = nullptr, *rch_beg = nullptr, *rch_end = nullptr, *rch_row = nullptr;
@@ -871,7 +871,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // variable, in variable-major slot order: pair records of the 3-literal
   // clauses whose first literal is the variable's own occurrence, then the
   // other pair records, then clause-row records.
-  std::vector<int32_t> row_ids, row_of, pair_first, pair_fneg, pair_mid, lrec_ptr, lrec_mid;
+  std::vector<int32_t> row_ids, row_of, pair_first, pair_fneg, pair_mid, lrec_ptr, lrec_mid, pair_end,
+      lrec_end;
   std::vector<int64_t> f_rbeg((size_t)F + 1, 0);
   std::vector<int2> pairs;
   std::vector<uint32_t> lrec;
@@ -1188,15 +1189,78 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
         for (int32_t i = 0; i < per && x * per + i < C; ++i) vorder[(size_t)i * kXcds + x] = x * per + i;
     }
     if (dsort) {
-      // item order within each variable chunk: costliest first, so the
-      // variables sharing a wave have similar occurrence counts
+      // item order within each variable chunk, so the variables sharing a
+      // wave run their loops the same number of times: costliest first, or
+      // in the flat plan by the trip counts of its three record loops
+      // (first-literal pairs, other pairs, clause rows; four records per
+      // trip), then whether it has clause rows at all (their inverse
+      // factors are set up once per variable)
+      std::vector<int64_t> key((size_t)n);
+      parallel_for(n, [&](int64_t v0, int64_t v1) {
+        for (int64_t v = v0; v < v1; ++v) {
+          if (!flat) {
+            key[v] = vcost[v];
+            continue;
+          }
+          const int64_t tf = std::min<int64_t>((pair_mid[v] - pair_first[v] + 3) / 4, 0xffff);
+          const int64_t tm = std::min<int64_t>((pair_first[v + 1] - pair_mid[v] + 3) / 4, 0xffff);
+          const int64_t nr = lrec_ptr[v + 1] - lrec_ptr[v];
+          key[v] = (tf << 33) | (tm << 17) | (std::min<int64_t>((nr + 3) / 4, 0xffff) << 1) |
+                   (nr > 0 ? 1 : 0);
+        }
+      });
       vperm.resize((size_t)n);
       for (int32_t v = 0; v < n; ++v) vperm[v] = v;
       parallel_for(vc.count(), [&](int64_t c0, int64_t c1) {
         for (int64_t cc = c0; cc < c1; ++cc)
           std::stable_sort(vperm.begin() + vc.beg[cc], vperm.begin() + vc.end[cc],
-                           [&](int32_t a2, int32_t b2) { return vcost[a2] > vcost[b2]; });
+                           [&](int32_t a2, int32_t b2) { return key[a2] > key[b2]; });
       });
+    }
+    if (flat) {
+      // record ranges as [begin, end) per variable; with an item order,
+      // the records are laid out in that order, so the variables sharing a
+      // wave read neighbouring records
+      pair_end.resize((size_t)std::max(n, 1));
+      lrec_end.resize((size_t)std::max(n, 1));
+      if (vperm.empty()) {
+        for (int32_t v = 0; v < n; ++v) {
+          pair_end[v] = pair_first[v + 1];
+          lrec_end[v] = lrec_ptr[v + 1];
+        }
+      } else {
+        std::vector<int64_t> pnew((size_t)n + 1, 0), lnew((size_t)n + 1, 0);
+        for (int32_t i = 0; i < n; ++i) {
+          const int32_t v = vperm[i];
+          pnew[i + 1] = pnew[i] + (pair_first[v + 1] - pair_first[v]);
+          lnew[i + 1] = lnew[i] + (lrec_ptr[v + 1] - lrec_ptr[v]);
+        }
+        std::vector<int2> pairs2(pairs.size());
+        std::vector<uint32_t> lrec2(lrec.size());
+        std::vector<int32_t> pb((size_t)std::max(n, 1)), pm2((size_t)std::max(n, 1)),
+            lb2((size_t)std::max(n, 1)), lm2((size_t)std::max(n, 1));
+        parallel_for(n, [&](int64_t i0, int64_t i1) {
+          for (int64_t i = i0; i < i1; ++i) {
+            const int32_t v = vperm[i];
+            std::copy(pairs.begin() + pair_first[v], pairs.begin() + pair_first[v + 1],
+                      pairs2.begin() + pnew[i]);
+            std::copy(lrec.begin() + lrec_ptr[v], lrec.begin() + lrec_ptr[v + 1],
+                      lrec2.begin() + lnew[i]);
+            pb[v] = (int32_t)pnew[i];
+            pm2[v] = (int32_t)(pnew[i] + (pair_mid[v] - pair_first[v]));
+            pair_end[v] = (int32_t)pnew[i + 1];
+            lb2[v] = (int32_t)lnew[i];
+            lm2[v] = (int32_t)(lnew[i] + (lrec_mid[v] - lrec_ptr[v]));
+            lrec_end[v] = (int32_t)lnew[i + 1];
+          }
+        });
+        pairs.swap(pairs2);
+        lrec.swap(lrec2);
+        pb.swap(pair_first);
+        pm2.swap(pair_mid);
+        lb2.swap(lrec_ptr);
+        lm2.swap(lrec_mid);
+      }
     }
     heavy_f_first[F] = (int32_t)heavy.size();
     h->vch = vc;
@@ -1482,11 +1546,12 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   if (flat) {
     UP(pairs, pairs);
     UP(pair_first, pair_first);
-    UP(pair_fneg, pair_fneg);
+    UP(pair_end, pair_end);
     UP(pair_mid, pair_mid);
     UP(lrec, lrec);
     UP(lrec_ptr, lrec_ptr);
     UP(lrec_mid, lrec_mid);
+    UP(lrec_end, lrec_end);
     UP(row_ids, row_ids);
     UP(rch_beg, c->rch.beg);
     UP(rch_end, c->rch.end);
@@ -1656,11 +1721,12 @@ VarPassArgs var_args(const galsat_ctx* h) {
   a.ldD = h->ldD;
   a.pairs = h->pairs;
   a.pair_first = h->pair_first;
-  a.pair_fneg = h->pair_fneg;
+  a.pair_end = h->pair_end;
   a.pair_mid = h->pair_mid;
   a.lrec = h->lrec;
   a.lrec_ptr = h->lrec_ptr;
   a.lrec_mid = h->lrec_mid;
+  a.lrec_end = h->lrec_end;
   a.prefetch = h->prefetch;
   a.qrow = h->qrow;
   a.ldq = h->ld;

@@ -69,12 +69,13 @@ struct VarPassArgs {
   // flat plan (galsat_flat.hip)
   const int2* pairs;            // [pairs] {other code 1 | own_neg << 31, other code 2}, codes
                                 // relative to the first variable of the formula
-  const int32_t* pair_first;    // [n+1] first pair of each variable (first-literal pairs first)
-  const int32_t* pair_fneg;     // [n] first first-literal pair of a negated own literal
+  const int32_t* pair_first;    // [n] first pair of each variable (first-literal pairs first)
+  const int32_t* pair_end;      // [n] end of each variable's pairs
   const int32_t* pair_mid;      // [n] first pair of each variable whose own literal is not first
   const uint32_t* lrec;         // [row records] clause row within the formula
-  const int32_t* lrec_ptr;      // [n+1] rows of positive own literals first, then negated
+  const int32_t* lrec_ptr;      // [n] first row record: positive own literals first, then negated
   const int32_t* lrec_mid;      // [n] first row record of a negated own literal
+  const int32_t* lrec_end;      // [n] end of each variable's row records
   const uint32_t* qrow;         // [clause rows][ldq] packed per-clause products
   int64_t ldq;
   const int32_t* chunk_fvb;     // [chunks] first variable of each variable chunk's formula
