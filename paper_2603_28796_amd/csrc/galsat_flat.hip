@@ -83,6 +83,12 @@ __device__ __forceinline__ void store_urow(uint32_t* __restrict__ p, const uint3
 
 }  // namespace
 
+// Byte offset of row idx (a formula-local index, below 2^24) at the given
+// row stride, plus a column offset: one 24-bit multiply-add.
+__device__ __forceinline__ uint32_t row_off(uint32_t idx, uint32_t stride_bytes, uint32_t col_bytes) {
+  return __umul24(idx, stride_bytes) + col_bytes;
+}
+
 // ---------------------------------------------------------------- row pass
 //
 // One item per clause of the row list (every clause that is not 3 literals
@@ -103,6 +109,10 @@ __global__ __launch_bounds__(kBlock) void k_row_clause(ClausePassArgs a) {
   const bool active = r0 < a.R;
   const int rc = active ? r0 : 0;
   const int cb = ldc(a.chunk_cbeg, chunk), ce = ldc(a.chunk_cend, chunk);
+  // the chunk's clauses belong to one formula: rows by 32-bit offsets from
+  // its first state row
+  const char* xb = reinterpret_cast<const char*>(a.x + (int64_t)ldc(a.chunk_fvb, chunk) * a.ldx);
+  const uint32_t ldx4 = (uint32_t)a.ldx * 4u, rc4 = (uint32_t)rc * 4u;
   double lsum[RPL];
   int usum[RPL];
 #pragma unroll
@@ -110,8 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_row_clause(ClausePassArgs a) {
 
   for (int i0 = cb + slot; i0 < ce; i0 += IPB) {
     const int i = uniform<LPI>(i0);
-    const int t = ldc(a.clause_ids, i);
-    const int ps = ldc(a.clause_ptr, t), pe = ldc(a.clause_ptr, t + 1);
+    const int ps = ldc(a.rlit_ptr, i), pe = ldc(a.rlit_ptr, i + 1);
     double qm[RPL];
     int qe[RPL], zeros[RPL];
     float mind[RPL];
@@ -123,20 +132,30 @@ __global__ __launch_bounds__(kBlock) void k_row_clause(ClausePassArgs a) {
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int pu = p + u < pe ? p + u : pe - 1;  // in bounds; masked below
-        codes[u] = ldc(a.clause_lits, pu);
-        load_row<RPL>(a.x + (int64_t)(codes[u] >> 1) * a.ldx + rc, y[u]);
+        codes[u] = ldc(a.rlits, pu);
+        load_row<RPL>(reinterpret_cast<const float*>(xb + row_off((uint32_t)codes[u] >> 1, ldx4, rc4)),
+                      y[u]);
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
+        // the factor as one FMA, f = fma(y, sg, sb) (as in the pair loop);
+        // a slot past the clause gets sg = 0, sb = 1, the factor exactly 1,
+        // which leaves the product and the zero count unchanged, and the
+        // margin 1 - 0.5 >= 0, which never decides the sign of the smallest
+        // margin
         const bool use = p + u < pe;
+        const bool neg = use && (codes[u] & 1) != 0;
+        const float sg = use ? (neg ? 1.0f : -1.0f) : 0.0f;
+        const float sb = neg ? 0.0f : 1.0f;
+        const float th = neg ? kHalfUp : kHalf;
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
-          const float f = lit_factor(codes[u], y[u][j]);
+          const float f = fmaf(y[u][j], sg, sb);
           const bool zero = f == 0.0f;
-          zeros[j] += (use && zero) ? 1 : 0;
-          qm[j] *= (use && !zero) ? (double)f : 1.0;
-          mind[j] = use ? fminf(mind[j], false_margin(codes[u], f)) : mind[j];
+          zeros[j] += zero ? 1 : 0;
+          qm[j] *= (double)(zero ? 1.0f : f);
+          mind[j] = fminf(mind[j], f - th);
         }
         if (u % 4 == 3) {
           // at most four factors since the last renormalisation: |qm| stays
@@ -172,10 +191,6 @@ __global__ __launch_bounds__(kBlock) void k_row_clause(ClausePassArgs a) {
 // and the load takes its base from scalar registers.  Record streams are
 // read once per step and are loaded non-temporally, and so is the next
 // state stored, so the gathered rows keep the L2.
-
-__device__ __forceinline__ uint32_t row_off(uint32_t idx, uint32_t stride_bytes, uint32_t col_bytes) {
-  return __umul24(idx, stride_bytes) + col_bytes;
-}
 
 // Pair records of [b, e) (consecutive pair slots of one variable), four at a
 // time with all eight row gathers in flight.  A literal's factor is one FMA,

@@ -192,7 +192,7 @@ struct galsat_ctx {
   uint32_t* lrec = nullptr;
   uint32_t* qrow = nullptr;  // [clause rows][ld] packed per-clause products
   int32_t *row_ids = nullptr, *rch_beg = nullptr, *rch_end = nullptr, *rch_row = nullptr;
-  int32_t* rch_order = nullptr;
+  int32_t *rch_order = nullptr, *rch_fvb = nullptr, *rlit_ptr = nullptr, *rlits = nullptr;
   int32_t n_rorder = 0;
   int32_t* vch_fvb = nullptr;  // [variable chunks] first variable of the chunk's formula
   int32_t* vch_rbase = nullptr;  // [variable chunks] first clause row of the chunk's formula
@@ -872,7 +872,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   // clauses whose first literal is the variable's own occurrence, then the
   // other pair records, then clause-row records.
   std::vector<int32_t> row_ids, row_of, pair_first, pair_fneg, pair_mid, lrec_ptr, lrec_mid, pair_end,
-      lrec_end;
+      lrec_end, rlit_ptr, rlits;
   std::vector<int64_t> f_rbeg((size_t)F + 1, 0);
   std::vector<int2> pairs;
   std::vector<uint32_t> lrec;
@@ -895,6 +895,20 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     }
     f_rbeg[F] = (int64_t)row_ids.size();
     for (size_t i = 0; i < row_ids.size(); ++i) row_of[row_ids[i]] = (int32_t)i;
+    // the row pass's own literal list: each listed clause's codes relative
+    // to its formula, contiguous in list order
+    rlit_ptr.assign(row_ids.size() + 1, 0);
+    for (size_t i = 0; i < row_ids.size(); ++i)
+      rlit_ptr[i + 1] = rlit_ptr[i] + (cp[row_ids[i] + 1] - cp[row_ids[i]]);
+    rlits.resize((size_t)std::max(rlit_ptr.back(), 1));
+    parallel_for((int64_t)row_ids.size(), [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        const int32_t t = row_ids[i];
+        const int32_t base2 = 2 * fvb[var_formula[cl[cp[t]] >> 1]];
+        int32_t o = rlit_ptr[i];
+        for (int32_t q = cp[t]; q < cp[t + 1]; ++q) rlits[(size_t)o++] = cl[q] - base2;
+      }
+    });
     std::vector<int64_t> np((size_t)n + 1, 0), nr((size_t)n + 1, 0), nf((size_t)n, 0),
         nfp((size_t)n, 0);
     parallel_for(n, [&](int64_t v0, int64_t v1) {
@@ -1557,6 +1571,14 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     UP(rch_end, c->rch.end);
     UP(rch_row, rrow);
     UP(rch_order, rorder);
+    UP(rlit_ptr, rlit_ptr);
+    UP(rlits, rlits);
+    {
+      std::vector<int32_t> rfvb((size_t)std::max(c->rch.count(), 1), 0);
+      for (int32_t f = 0; f < F; ++f)
+        for (int cc = c->rch.f_first[f]; cc < c->rch.f_first[f + 1]; ++cc) rfvb[cc] = fvb[f];
+      UP(rch_fvb, rfvb);
+    }
     c->n_rorder = (int32_t)rorder.size();
     std::vector<int32_t> vfvb((size_t)std::max(VC, 1), 0);
     for (int32_t f = 0; f < F; ++f)
@@ -1835,6 +1857,9 @@ galsat_status flat_passes(galsat_ctx* h, VarPassArgs va, Tile t, int mode, int f
     ca.R = h->R;
     ca.qrow = h->qrow;
     ca.ldq = h->ld;
+    ca.rlit_ptr = h->rlit_ptr;
+    ca.rlits = h->rlits;
+    ca.chunk_fvb = h->rch_fvb;
     ProfScope _ps(h, GALSAT_K_CLAUSE_PASS, s);
     GS_HIP(h, launch_row_clause(ca, t, blocks, s), "clause-row pass");
   }

@@ -110,6 +110,9 @@ struct ClausePassArgs {
   int32_t R;
   uint32_t* qrow;               // row pass of the flat plan: [list][ldq] packed clause values
   int64_t ldq;
+  const int32_t* rlit_ptr;      // row pass: [list + 1] literals of each listed clause in rlits
+  const int32_t* rlits;         // row pass: literal codes relative to the formula (code - 2 vbeg)
+  const int32_t* chunk_fvb;     // row pass: [chunks] first variable of the chunk's formula
 };
 
 struct FinalizeArgs {
