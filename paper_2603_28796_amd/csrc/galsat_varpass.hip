@@ -354,9 +354,22 @@ __global__ __launch_bounds__(kBlock) void k_heavy_finish(VarPassArgs a, int h0, 
     double g[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; ++j) g[j] = 0.0;
-    for (int sgi = sb + slot; sgi < se; sgi += IPB) {
+    // eight of the slot's segments per trip, all loads issued first (indices
+    // clamped into range), then added in segment order
+    for (int sgi = sb + slot; sgi < se; sgi += 8 * IPB) {
+      double d[8][RPL];
 #pragma unroll
-      for (int j = 0; j < RPL; ++j) g[j] += a.gseg[(int64_t)sgi * a.R + rc + j];
+      for (int u = 0; u < 8; ++u) {
+        const int s2 = min(sgi + u * IPB, se - 1);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) d[u][j] = a.gseg[(int64_t)s2 * a.R + rc + j];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (sgi + u * IPB < se) {
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) g[j] += d[u][j];
+        }
     }
 #pragma unroll
     for (int j = 0; j < RPL; ++j) s_g[slot][lane * RPL + j] = g[j];
