@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_flat_seg(VarPassArgs a) {
 #pragma unroll
   for (int j = 0; j < RPL; ++j) { lsum[j] = 0.0; usum[j] = 0; }
   for (int s0 = sb + slot; s0 < se; s0 += IPB) {
-    const int sgi = uniform<LPI>(s0);
+    const int sgi = uniform<LPI>(ldc(a.seg_perm, s0));
     const int v = ldc(a.seg_var, sgi);
     const int qv = ldc(a.var_ptr, v);
     const int f = ldc(a.var_formula, v);

@@ -197,7 +197,7 @@ struct galsat_ctx {
   int32_t* vch_fvb = nullptr;  // [variable chunks] first variable of the chunk's formula
   int32_t* vch_rbase = nullptr;  // [variable chunks] first clause row of the chunk's formula
   int32_t* f_rbeg = nullptr;     // [F+1] first clause row of each formula
-  int32_t *seg_var = nullptr, *seg_q0 = nullptr, *seg_q1 = nullptr;
+  int32_t *seg_var = nullptr, *seg_q0 = nullptr, *seg_q1 = nullptr, *seg_perm = nullptr;
   int32_t *heavy_var = nullptr, *heavy_sbeg = nullptr;
   int32_t *fin_step_a0 = nullptr, *fin_step_a1 = nullptr;
   int32_t *fin_all_a0 = nullptr, *fin_all_a1 = nullptr;
@@ -403,12 +403,14 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // (0: the LDS schedule issues formulas in index order), xpin (1/0: the
 // single pass maps restart tiles to XCDs or not), flat (1/0: the flat plan
 // of pair records and clause rows, or not), pf (flat plan: 1/0, records of
-// the next batch prefetched or not) and rsort (flat plan: 1/0, a variable's
-// clause rows in row order or in slot order).
+// the next batch prefetched or not), rsort (flat plan: 1/0, a variable's
+// clause rows in row order or in slot order) and sord (flat plan: 1/0,
+// segments of split variables run in the order of the first clause row
+// they read, or variable by variable).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
                     int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
                     int* short_clauses, int* xseq, int* segdiv, int* ldsrg, int* ldsstage,
-                    int* ldslpt, int* xpin, int* flat, int* pf, int* rsort) {
+                    int* ldslpt, int* xpin, int* flat, int* pf, int* rsort, int* sord) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -438,6 +440,7 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "ldslpt") *ldslpt = v;
       else if (k == "xpin") *xpin = v;
       else if (k == "flat") *flat = v;
+      else if (k == "sord") *sord = v;
       else if (k == "pf") *pf = v;
       else if (k == "rsort") *rsort = v;
     }
@@ -623,9 +626,10 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
   int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1, segdiv_o = -1;
   int ldsrg_o = 0, ldsstage_o = -1, ldslpt_o = -1, xpin_o = -1, flat_o = -1, pf_o = -1, rsort_o = -1;
+  int sord_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
                  &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o, &ldsrg_o, &ldsstage_o,
-                 &ldslpt_o, &xpin_o, &flat_o, &pf_o, &rsort_o);
+                 &ldslpt_o, &xpin_o, &flat_o, &pf_o, &rsort_o, &sord_o);
   const bool csort = csort_o != 0;
   // Persistent LDS schedule: every formula's restart group must fit in LDS
   // (state double-buffered); SGD only; every clause recomputed.
@@ -1052,7 +1056,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   const int tiles = (R + h->tile.tile() - 1) / h->tile.tile();
   const int64_t chunks_target = std::max<int64_t>(1, kTargetBlocks / std::max(1, tiles));
   const int ipb = kBlock / h->tile.lpi;
-  std::vector<int32_t> heavy, heavy_sbeg{0}, seg_var, seg_q0, seg_q1, vorder, oorder, vperm;
+  std::vector<int32_t> heavy, heavy_sbeg{0}, seg_var, seg_q0, seg_q1, vorder, oorder, vperm, seg_perm;
   std::vector<int64_t> fcost_all((size_t)F, 0);  // gather cost of each formula
   std::vector<int32_t> heavy_f_first((size_t)F + 1, 0);
   {
@@ -1156,15 +1160,33 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       // otherwise
       sc.f_first[f] = sc.count();
       const int32_t s_lo = heavy_sbeg[heavy_f_first[f]], s_hi = (int32_t)seg_var.size();
+      // run order of the formula's segments (chunks cover runs of it).  In
+      // the flat plan by the first clause row a segment reads (segments of
+      // pair records only first): the hot variables each sweep the clause
+      // rows in row order, so segments of different variables that run at
+      // the same time read the same rows
+      for (int32_t sg = s_lo; sg < s_hi; ++sg) seg_perm.push_back(sg);
+      if (flat && sord_o != 0 && s_hi > s_lo) {
+        std::vector<int64_t> skey((size_t)(s_hi - s_lo));
+        for (int32_t sg = s_lo; sg < s_hi; ++sg) {
+          const int32_t v = seg_var[sg];
+          const int64_t npv = pair_first[v + 1] - pair_first[v];
+          const int64_t u0 = seg_q0[sg] - vp[v], u1 = seg_q1[sg] - vp[v];
+          skey[sg - s_lo] = u1 <= npv ? -1 : (int64_t)lrec[(size_t)(lrec_ptr[v] + std::max(u0, npv) - npv)];
+        }
+        std::stable_sort(seg_perm.begin() + s_lo, seg_perm.end(),
+                         [&](int32_t a2, int32_t b2) { return skey[a2 - s_lo] < skey[b2 - s_lo]; });
+      }
       int32_t sb = s_lo;
       int64_t sacc = 0;
       const int64_t seg_target = flat ? std::max<int64_t>(64, seg_cap * ipb) : target_f;
-      for (int32_t sg = s_lo; sg < s_hi; ++sg) {
+      for (int32_t i = s_lo; i < s_hi; ++i) {
+        const int32_t sg = seg_perm[i];
         for (int32_t q = seg_q0[sg]; q < seg_q1[sg]; ++q) sacc += occ_cost[q];
-        if (sacc >= seg_target || sg + 1 == s_hi) {
+        if (sacc >= seg_target || i + 1 == s_hi) {
           sc.beg.push_back(sb);
-          sc.end.push_back(sg + 1);
-          sb = sg + 1;
+          sc.end.push_back(i + 1);
+          sb = i + 1;
           sacc = 0;
         }
       }
@@ -1598,6 +1620,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(ach_beg, c->ach.beg);
   UP(ach_end, c->ach.end);
   UP(seg_var, seg_var);
+  UP(seg_perm, seg_perm);
   UP(seg_q0, seg_q0);
   UP(seg_q1, seg_q1);
   UP(heavy_var, heavy);
@@ -1728,6 +1751,7 @@ VarPassArgs var_args(const galsat_ctx* h) {
   a.chunk_vend = h->vch_end;
   a.chunk_row = h->vch_row;
   a.seg_var = h->seg_var;
+  a.seg_perm = h->seg_perm;
   a.seg_q0 = h->seg_q0;
   a.seg_q1 = h->seg_q1;
   a.gseg = h->gseg;

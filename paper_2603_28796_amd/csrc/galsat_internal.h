@@ -35,6 +35,7 @@ struct VarPassArgs {
   const int32_t* chunk_row;     // [chunks] partial-sum row of each chunk
   const int32_t* chunk_order;   // [blocks] chunk of each workgroup (-1: none), or null
   const int32_t* seg_var;       // [segments] variable of each segment of a split variable
+  const int32_t* seg_perm;      // [segments] run order: segment chunks cover runs of it
   const int32_t* seg_q0;        // [segments] occurrence range of the segment
   const int32_t* seg_q1;
   double* gseg;                 // [segments][R] partial gradients of the segments
