@@ -170,8 +170,13 @@ typedef struct {
                               id, 0: off; on by default for one formula with at least
                               1,024 restarts), flat (1: the flat gradient, 0: not; on by
                               default for at most 64 restarts with AUTO partials and no
-                              two= or krec= key).  Keys left out take the plan's own
-                              choice. */
+                              two= or krec= key), and for the flat plan pf (1/0: records
+                              of the next batch loaded during the current one's
+                              gathers; on by default from 24 occurrences per variable),
+                              rsort (1/0: a variable's clause-row records in row order,
+                              default 1) and sord (1/0: split-variable segments run in
+                              the order of the first clause row they read, default 1).
+                              Keys left out take the plan's own choice. */
 } galsat_options;
 
 /* Fills *opt with the defaults listed above. */
