@@ -484,15 +484,26 @@ __global__ void k_zero_i32(int32_t* p, int64_t count) {
 // ------------------------------------------------------- round & count
 //
 // bits[w][v]: bit l = [x[v][64w + l] > 0.5] packed by one wavefront ballot.
+// A wave takes kPackU consecutive variables per trip, all their loads
+// issued before the ballots.
+constexpr int kPackU = 8;
+
 __global__ __launch_bounds__(256) void k_pack_bits(const float* x, int32_t ldx, int32_t n,
                                                    int32_t R, uint64_t* bits) {
   const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int word = blockIdx.y;
   const int r = word * 64 + lane;
-  for (int64_t v = (int64_t)blockIdx.x * 4 + wv; v < n; v += (int64_t)gridDim.x * 4) {
-    const bool one = (r < R) && (x[v * ldx + r] > 0.5f);
-    const uint64_t m = __ballot(one);
-    if (lane == 0) bits[(int64_t)word * n + v] = m;
+  for (int64_t v0 = ((int64_t)blockIdx.x * 4 + wv) * kPackU; v0 < n;
+       v0 += (int64_t)gridDim.x * 4 * kPackU) {
+    float val[kPackU];
+#pragma unroll
+    for (int u = 0; u < kPackU; ++u)
+      val[u] = (r < R && v0 + u < n) ? x[(v0 + u) * ldx + r] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < kPackU; ++u) {
+      const uint64_t m = __ballot(val[u] > 0.5f);
+      if (lane == 0 && v0 + u < n) bits[(int64_t)word * n + v0 + u] = m;
+    }
   }
 }
 
@@ -500,14 +511,17 @@ __global__ __launch_bounds__(256) void k_pack_bits(const float* x, int32_t ldx, 
 // "unsatisfied" mask is the AND over its literals of "literal false".  The
 // per-restart count over the wave's 64 clauses is then one ballot and one
 // popcount per restart, accumulated by the lane that owns the restart.
+// order: block -> chunk (-1: nothing), or null.
 __global__ __launch_bounds__(256) void k_count_unsat(const int32_t* clause_ptr,
                                                      const int32_t* clause_lits,
                                                      const int32_t* chunk_cbeg,
                                                      const int32_t* chunk_cend,
+                                                     const int32_t* order,
                                                      const uint64_t* bits, int32_t n, int32_t R,
                                                      int32_t* unsat_part) {
   const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int chunk = blockIdx.x, word = blockIdx.y;
+  const int chunk = order ? order[blockIdx.x] : (int)blockIdx.x, word = blockIdx.y;
+  if (chunk < 0) return;  // padding of the XCD-aware order: the whole block leaves
   const int cb = chunk_cbeg[chunk], ce = chunk_cend[chunk];
   const int rem = R - word * 64;
   const uint64_t valid = rem >= 64 ? ~0ULL : ((1ULL << rem) - 1ULL);
@@ -721,19 +735,20 @@ hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s) {
 hipError_t launch_pack_bits(const float* x, int32_t ldx, int32_t n, int32_t R, uint64_t* bits,
                             hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  dim3 grid(grid_x_for(((int64_t)n + 3) / 4), (R + 63) / 64), block(256);
+  dim3 grid(grid_x_for(((int64_t)n + 4 * kPackU - 1) / (4 * kPackU)), (R + 63) / 64), block(256);
   hipLaunchKernelGGL(k_pack_bits, grid, block, 0, s, x, ldx, n, R, bits);
   return hipGetLastError();
 }
 
 hipError_t launch_count_unsat(const int32_t* clause_ptr, const int32_t* clause_lits,
-                              const int32_t* chunk_cbeg, const int32_t* chunk_cend, int chunks,
+                              const int32_t* chunk_cbeg,
+                              const int32_t* chunk_cend, const int32_t* order, int blocks,
                               const uint64_t* bits, int32_t n, int32_t R, int32_t* unsat_part,
                               hipStream_t s) {
-  if (chunks <= 0) return hipSuccess;
-  dim3 grid(chunks, (R + 63) / 64), block(256);
+  if (blocks <= 0) return hipSuccess;
+  dim3 grid(blocks, (R + 63) / 64), block(256);
   hipLaunchKernelGGL(k_count_unsat, grid, block, 0, s, clause_ptr, clause_lits, chunk_cbeg,
-                     chunk_cend, bits, n, R, unsat_part);
+                     chunk_cend, order, bits, n, R, unsat_part);
   return hipGetLastError();
 }
 

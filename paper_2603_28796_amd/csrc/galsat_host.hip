@@ -184,7 +184,8 @@ struct galsat_ctx {
   };
   std::vector<ClauseClass> cls;
   int32_t *segch_beg = nullptr, *segch_end = nullptr, *segch_row = nullptr;
-  int32_t *ach_beg = nullptr, *ach_end = nullptr;
+  int32_t *ach_beg = nullptr, *ach_end = nullptr, *ach_order = nullptr;
+  int32_t n_aorder = 0;  // blocks of the XCD-aware order of the all-clause chunks, 0: none
   // flat plan
   int2* pairs = nullptr;
   int32_t *pair_first = nullptr, *pair_end = nullptr, *pair_mid = nullptr, *lrec_ptr = nullptr,
@@ -1405,7 +1406,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   }
   // flat plan: chunks of the clause-row list, in the same formula groups
   // of the XCD-aware order as the variable chunks
-  std::vector<int32_t> rorder;
+  std::vector<int32_t> rorder, aorder;
   if (flat) {
     std::vector<int64_t> pre(row_ids.size() + 1, 0);
     for (size_t i = 0; i < row_ids.size(); ++i)
@@ -1426,7 +1427,18 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   {
     std::vector<int64_t> pre((size_t)m + 1, 0), fb(fcb.begin(), fcb.end());
     for (int32_t t = 0; t < m; ++t) pre[t + 1] = pre[t] + 1 + (cp[t + 1] - cp[t]);
-    h->ach = make_chunks(F, fb, pre, std::max<int64_t>(256, pre[m] / chunks_target));
+    if (xcd_all) {
+      // several formulas: about xcd_chunks chunks per formula in the
+      // XCD-aware order, so an XCD's resident workgroups count a few
+      // formulas at a time and their packed rows stay in its L2
+      std::vector<int64_t> ft((size_t)F);
+      for (int32_t f = 0; f < F; ++f)
+        ft[f] = std::max<int64_t>(256, (pre[fcb[f + 1]] - pre[fcb[f]]) / xcd_chunks);
+      h->ach = make_chunks(F, fb, pre, 0, &ft);
+      xcd_order_all(h->ach, &aorder);
+    } else {
+      h->ach = make_chunks(F, fb, pre, std::max<int64_t>(256, pre[m] / chunks_target));
+    }
   }
   ptimer.mark("chunks");
   h->heavy_f_first = heavy_f_first;
@@ -1619,6 +1631,8 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   UP(segch_row, grow);
   UP(ach_beg, c->ach.beg);
   UP(ach_end, c->ach.end);
+  UP(ach_order, aorder);
+  c->n_aorder = (int32_t)aorder.size();
   UP(seg_var, seg_var);
   UP(seg_perm, seg_perm);
   UP(seg_q0, seg_q0);
@@ -2399,8 +2413,10 @@ extern "C" galsat_status galsat_round_check(galsat_handle h, const float* x, int
   }
   {
     ProfScope _ps(h, GALSAT_K_COUNT, s);
-    GS_HIP(h, launch_count_unsat(h->clause_ptr, h->clause_lits, h->ach_beg, h->ach_end, h->ach.count(),
-                                 h->bits, h->n, h->R, h->unsat_part, s),
+    GS_HIP(h, launch_count_unsat(h->clause_ptr, h->clause_lits, h->ach_beg, h->ach_end,
+                                 h->n_aorder > 0 ? h->ach_order : nullptr,
+                                 h->n_aorder > 0 ? h->n_aorder : h->ach.count(), h->bits, h->n,
+                                 h->R, h->unsat_part, s),
            "count unsat");
   }
   FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->zero_empty, h->loss_part, h->unsat_part,
@@ -2488,8 +2504,10 @@ extern "C" galsat_status galsat_round_check_static(galsat_handle h, const float*
   // either (creating one may allocate)
   hipStream_t s = static_cast<hipStream_t>(stream);
   GS_HIP(h, launch_pack_bits(x, ldx, h->n, h->R, bits, s), "pack bits");
-  GS_HIP(h, launch_count_unsat(h->clause_ptr, h->clause_lits, h->ach_beg, h->ach_end, h->ach.count(),
-                               bits, h->n, h->R, rows, s),
+  GS_HIP(h, launch_count_unsat(h->clause_ptr, h->clause_lits, h->ach_beg, h->ach_end,
+                               h->n_aorder > 0 ? h->ach_order : nullptr,
+                               h->n_aorder > 0 ? h->n_aorder : h->ach.count(), bits, h->n, h->R,
+                               rows, s),
          "count unsat");
   FinalizeArgs fa{h->fin_all_a0, h->fin_all_a1, h->zero_empty, nullptr, rows,
                   nullptr, unsat, h->R, 0, part_l, part_u, 1, h->max_all_rows};

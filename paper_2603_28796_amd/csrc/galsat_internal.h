@@ -213,7 +213,8 @@ hipError_t launch_copy_state(const float* src, int32_t lds, float* dst, int32_t 
 hipError_t launch_pack_bits(const float* x, int32_t ldx, int32_t n, int32_t R, uint64_t* bits,
                             hipStream_t s);
 hipError_t launch_count_unsat(const int32_t* clause_ptr, const int32_t* clause_lits,
-                              const int32_t* chunk_cbeg, const int32_t* chunk_cend, int chunks,
+                              const int32_t* chunk_cbeg,
+                              const int32_t* chunk_cend, const int32_t* order, int blocks,
                               const uint64_t* bits, int32_t n, int32_t R, int32_t* unsat_part,
                               hipStream_t s);
 hipError_t launch_best(const int32_t* unsat, int32_t F, int32_t R, int32_t* best, hipStream_t s);
