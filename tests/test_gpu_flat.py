@@ -163,3 +163,28 @@ def test_flat_default_for_narrow_batches():
     cnf = CASES["long_mix"]()
     lens = np.diff(cnf.clause_ptr)
     assert info["clause_rows"] == int(((lens != 3) & (lens > 0)).sum())
+
+
+@pytest.mark.parametrize("case", ["long_mix", "mixed20k", "batch"])
+def test_flat_orders_leave_every_sum_unchanged(case):
+    """The trip-count order of a chunk's variables (and the record layout
+    that follows it), the run order of split-variable segments and record
+    prefetching change which wave does what, never the order of any
+    variable's sum: the state and the unsat trace after two fused steps are
+    bitwise those of the plan with each of them turned off."""
+    say(f"[flat orders] {case}")
+    cnf = CASES[case]()
+    R = 16
+    x = _x0(cnf.n, R, 41)
+    ref = None
+    for plan in ("", "dsort=0", "sord=0", "pf=1", "pf=0", "dsort=0,sord=0"):
+        prob = _flat(cnf, R, plan)
+        xs = x.clone()
+        lt, ut = prob.step(xs, 2, trace=True)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = (xs, ut, lt)
+        else:
+            assert torch.equal(xs, ref[0]) and torch.equal(ut, ref[1]), plan
+            assert torch.allclose(lt, ref[2], rtol=1e-6, atol=0), plan
+        prob.close()
