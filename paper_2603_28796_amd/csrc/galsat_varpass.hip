@@ -35,8 +35,27 @@ __device__ __forceinline__ void inline4(const VarPassArgs& a, const int4 (&o)[4]
   }
 }
 
+// The product of the first K of up to seven other literals (codes), all K
+// gathers in flight.
+template <int RPL, int K>
+__device__ __forceinline__ void others_k(const VarPassArgs& a, const int (&all)[7], int nother,
+                                         bool first, int r0, float (&prod)[RPL],
+                                         bool (&any_true)[RPL]) {
+  int codes[K];
+  float y[K][RPL];
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    codes[c] = all[c];
+    load_row<RPL>(a.x + (int64_t)(codes[c] >> 1) * a.ldx + r0, y[c]);
+  }
+  combine<RPL, K>(codes, y, nother, first, prod, any_true);
+}
+
 // One INLINE occurrence of up to 7 other literals, all gathers in flight.
-template <int RPL>
+// U: the record is the same for the whole wave (one item per wave), so a
+// record of 4 to 7 other literals branches, without divergence, to the
+// instance of exactly its size instead of padding to seven.
+template <int RPL, bool U = false>
 __device__ __forceinline__ void inline_one(const VarPassArgs& a, const int4 o, int q, int r0,
                                            const float (&xv)[RPL], double (&g)[RPL],
                                            double (&lsum)[RPL], int (&usum)[RPL]) {
@@ -49,6 +68,14 @@ __device__ __forceinline__ void inline_one(const VarPassArgs& a, const int4 o, i
 #pragma unroll
     for (int c = 0; c < 3; ++c) load_row<RPL>(a.x + (int64_t)(codes[c] >> 1) * a.ldx + r0, y[c]);
     combine<RPL, 3>(codes, y, nother, rec_first(hdr), prod, any_true);
+  } else if constexpr (U) {
+    const int4 e = ldc4(a.occx, q);
+    const int all[7] = {o.y, o.z, o.w, e.x, e.y, e.z, e.w};
+    const bool first = rec_first(hdr);
+    if (nother == 4) others_k<RPL, 4>(a, all, nother, first, r0, prod, any_true);
+    else if (nother == 5) others_k<RPL, 5>(a, all, nother, first, r0, prod, any_true);
+    else if (nother == 6) others_k<RPL, 6>(a, all, nother, first, r0, prod, any_true);
+    else others_k<RPL, 7>(a, all, nother, first, r0, prod, any_true);
   } else {
     const int4 e = ldc4(a.occx, q);
     const int codes[7] = {o.y, o.z, o.w, e.x, e.y, e.z, e.w};
@@ -60,8 +87,36 @@ __device__ __forceinline__ void inline_one(const VarPassArgs& a, const int4 o, i
   add_occurrence<RPL>(rec_neg(hdr), rec_first(hdr), prod, any_true, xv, g, lsum, usum);
 }
 
-// One GENERAL occurrence: the clause's other literals four at a time.
-template <int RPL>
+// W consecutive literal positions [i, i + W) of a GENERAL record's clause
+// (ce: the clause's end, p: the own position) multiplied into prod, all W
+// gathers in flight; positions past ce (when W overruns it) read the
+// clause's first literal again and, like the own position, count as 1.
+template <int RPL, int W>
+__device__ __forceinline__ void general_batch(const VarPassArgs& a, int i, int cs, int ce, int p,
+                                              int r0, float (&prod)[RPL], bool (&any_true)[RPL]) {
+  int codes[W];
+  float y[W][RPL];
+#pragma unroll
+  for (int u = 0; u < W; ++u) {
+    const int iu = i + u < ce ? i + u : cs;
+    codes[u] = ldc(a.clause_lits, iu);
+    load_row<RPL>(a.x + (int64_t)(codes[u] >> 1) * a.ldx + r0, y[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < W; ++u) {
+    const bool use = i + u < ce && i + u != p;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      prod[j] *= use ? lit_factor(codes[u], y[u][j]) : 1.0f;
+      any_true[j] = any_true[j] || (use && lit_true(codes[u], y[u][j]));
+    }
+  }
+}
+
+// One GENERAL occurrence: the clause's other literals four at a time.  U
+// (one item per wave): the last one to three positions run as an instance
+// of exactly that width instead of four.
+template <int RPL, bool U = false>
 __device__ __forceinline__ void general_one(const VarPassArgs& a, const int4 o, int r0,
                                             const float (&xv)[RPL], double (&g)[RPL],
                                             double (&lsum)[RPL], int (&usum)[RPL]) {
@@ -72,32 +127,41 @@ __device__ __forceinline__ void general_one(const VarPassArgs& a, const int4 o, 
   bool any_true[RPL];
 #pragma unroll
   for (int j = 0; j < RPL; ++j) { prod[j] = 1.0f; any_true[j] = false; }
-  for (int i = cs; i < ce; i += 4) {
-    int codes[4];
-    float y[4][RPL];
+  if constexpr (U) {
+    int i = cs;
+    for (; i + 4 <= ce; i += 4) general_batch<RPL, 4>(a, i, cs, ce, p, r0, prod, any_true);
+    const int rem = ce - i;
+    if (rem == 1) general_batch<RPL, 1>(a, i, cs, ce, p, r0, prod, any_true);
+    else if (rem == 2) general_batch<RPL, 2>(a, i, cs, ce, p, r0, prod, any_true);
+    else if (rem == 3) general_batch<RPL, 3>(a, i, cs, ce, p, r0, prod, any_true);
+  } else {
+    for (int i = cs; i < ce; i += 4) {
+      int codes[4];
+      float y[4][RPL];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      // positions past the clause read the clause's first literal again and
-      // are masked out below, like the own position
-      const int iu = i + u < ce ? i + u : cs;
-      codes[u] = ldc(a.clause_lits, iu);
-      load_row<RPL>(a.x + (int64_t)(codes[u] >> 1) * a.ldx + r0, y[u]);
-    }
+      for (int u = 0; u < 4; ++u) {
+        // positions past the clause read the clause's first literal again
+        // and are masked out below, like the own position
+        const int iu = i + u < ce ? i + u : cs;
+        codes[u] = ldc(a.clause_lits, iu);
+        load_row<RPL>(a.x + (int64_t)(codes[u] >> 1) * a.ldx + r0, y[u]);
+      }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool use = i + u < ce && i + u != p;
+      for (int u = 0; u < 4; ++u) {
+        const bool use = i + u < ce && i + u != p;
 #pragma unroll
-      for (int j = 0; j < RPL; ++j) {
-        prod[j] *= use ? lit_factor(codes[u], y[u][j]) : 1.0f;
-        any_true[j] = any_true[j] || (use && lit_true(codes[u], y[u][j]));
+        for (int j = 0; j < RPL; ++j) {
+          prod[j] *= use ? lit_factor(codes[u], y[u][j]) : 1.0f;
+          any_true[j] = any_true[j] || (use && lit_true(codes[u], y[u][j]));
+        }
       }
     }
   }
   add_occurrence<RPL>((ldc(a.clause_lits, p) & 1) != 0, first, prod, any_true, xv, g, lsum, usum);
 }
 
-// One occurrence of any kind.
-template <int RPL>
+// One occurrence of any kind (U: as for inline_one).
+template <int RPL, bool U = false>
 __device__ __forceinline__ void one_occurrence(const VarPassArgs& a, const int4 o, int q, int r0,
                                                const float (&xv)[RPL], double (&g)[RPL],
                                                double (&lsum)[RPL], int (&usum)[RPL]) {
@@ -108,9 +172,9 @@ __device__ __forceinline__ void one_occurrence(const VarPassArgs& a, const int4 
 #pragma unroll
     for (int j = 0; j < RPL; ++j) g[j] += (double)d[j];
   } else if (kind == kRecInline) {
-    inline_one<RPL>(a, o, q, r0, xv, g, lsum, usum);
+    inline_one<RPL, U>(a, o, q, r0, xv, g, lsum, usum);
   } else {
-    general_one<RPL>(a, o, r0, xv, g, lsum, usum);
+    general_one<RPL, U>(a, o, r0, xv, g, lsum, usum);
   }
 }
 
@@ -119,7 +183,7 @@ __device__ __forceinline__ void one_occurrence(const VarPassArgs& a, const int4 
 // (lanes past the last restart pass a clamped one and discard the results),
 // so the loop runs under wave-uniform control and its table loads can be
 // scalar.
-template <int RPL>
+template <int RPL, bool U = false>
 __device__ __forceinline__ void gather_occurrences(const VarPassArgs& a, int q0, int q1, int r0,
                                                    const float (&xv)[RPL], double (&g)[RPL],
                                                    double (&lsum)[RPL], int (&usum)[RPL]) {
@@ -139,7 +203,7 @@ __device__ __forceinline__ void gather_occurrences(const VarPassArgs& a, int q0,
           inline4<RPL, 3>(a, o, r0, xv, g, lsum, usum);
         } else {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) inline_one<RPL>(a, o[k], q + k, r0, xv, g, lsum, usum);
+          for (int k = 0; k < 4; ++k) inline_one<RPL, U>(a, o[k], q + k, r0, xv, g, lsum, usum);
         }
         q += 4;
         continue;
@@ -156,7 +220,7 @@ __device__ __forceinline__ void gather_occurrences(const VarPassArgs& a, int q0,
         continue;
       }
     }
-    one_occurrence<RPL>(a, ldc4(a.occ, q), q, r0, xv, g, lsum, usum);
+    one_occurrence<RPL, U>(a, ldc4(a.occ, q), q, r0, xv, g, lsum, usum);
     ++q;
   }
 }
@@ -299,7 +363,9 @@ __global__ __launch_bounds__(kBlock) void k_var_stream(VarPassArgs a) {
 // item should serialise): each segment's partial gradient goes to
 // gseg[s][r] in FP64.  With one item per wave the segment walks are
 // latency-bound chains of gathers, and six waves per SIMD (a few spilled
-// registers) beat five without spills.
+// registers) beat five without spills; records then take their exact-size
+// instances (in the whole-variable kernel the extra registers of those
+// instances cost more than they save).
 template <int LPI, int RPL>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(LPI == 64 ? 6 : 1))) void k_var_seg(VarPassArgs a) {
@@ -325,7 +391,7 @@ __attribute__((amdgpu_waves_per_eu(LPI == 64 ? 6 : 1))) void k_var_seg(VarPassAr
 #pragma unroll
     for (int j = 0; j < RPL; ++j) g[j] = 0.0;
     load_row<RPL>(a.x + (int64_t)v * a.ldx + rc, xv);
-    gather_occurrences<RPL>(a, ldc(a.seg_q0, sgi), ldc(a.seg_q1, sgi), rc, xv, g, lsum, usum);
+    gather_occurrences<RPL, LPI == 64>(a, ldc(a.seg_q0, sgi), ldc(a.seg_q1, sgi), rc, xv, g, lsum, usum);
     if (active) {
 #pragma unroll
       for (int j = 0; j < RPL; ++j) a.gseg[(int64_t)sgi * a.R + r0 + j] = g[j];
