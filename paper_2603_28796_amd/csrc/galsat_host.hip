@@ -1228,7 +1228,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
     if (dsort) {
       // item order within each variable chunk, so the variables sharing a
       // wave run their loops the same number of times: costliest first, or
-      // in the flat plan by the trip counts of its three record loops
+      // in the flat plan by the trip counts of their three record loops
       // (first-literal pairs, other pairs, clause rows; four records per
       // trip), then whether it has clause rows at all (their inverse
       // factors are set up once per variable)
