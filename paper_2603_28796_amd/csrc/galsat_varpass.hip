@@ -35,12 +35,12 @@ __device__ __forceinline__ void inline4(const VarPassArgs& a, const int4 (&o)[4]
   }
 }
 
-// The product of the first K of up to seven other literals (codes), all K
-// gathers in flight.
+// The product of a record's exactly K other literals (the first K of
+// `all`), all K gathers in flight; no slot is padding, so combine's masks
+// fold away.
 template <int RPL, int K>
-__device__ __forceinline__ void others_k(const VarPassArgs& a, const int (&all)[7], int nother,
-                                         bool first, int r0, float (&prod)[RPL],
-                                         bool (&any_true)[RPL]) {
+__device__ __forceinline__ void others_k(const VarPassArgs& a, const int (&all)[7], bool first,
+                                         int r0, float (&prod)[RPL], bool (&any_true)[RPL]) {
   int codes[K];
   float y[K][RPL];
 #pragma unroll
@@ -48,7 +48,7 @@ __device__ __forceinline__ void others_k(const VarPassArgs& a, const int (&all)[
     codes[c] = all[c];
     load_row<RPL>(a.x + (int64_t)(codes[c] >> 1) * a.ldx + r0, y[c]);
   }
-  combine<RPL, K>(codes, y, nother, first, prod, any_true);
+  combine<RPL, K>(codes, y, K, first, prod, any_true);
 }
 
 // One INLINE occurrence of up to 7 other literals, all gathers in flight.
@@ -72,10 +72,10 @@ __device__ __forceinline__ void inline_one(const VarPassArgs& a, const int4 o, i
     const int4 e = ldc4(a.occx, q);
     const int all[7] = {o.y, o.z, o.w, e.x, e.y, e.z, e.w};
     const bool first = rec_first(hdr);
-    if (nother == 4) others_k<RPL, 4>(a, all, nother, first, r0, prod, any_true);
-    else if (nother == 5) others_k<RPL, 5>(a, all, nother, first, r0, prod, any_true);
-    else if (nother == 6) others_k<RPL, 6>(a, all, nother, first, r0, prod, any_true);
-    else others_k<RPL, 7>(a, all, nother, first, r0, prod, any_true);
+    if (nother == 4) others_k<RPL, 4>(a, all, first, r0, prod, any_true);
+    else if (nother == 5) others_k<RPL, 5>(a, all, first, r0, prod, any_true);
+    else if (nother == 6) others_k<RPL, 6>(a, all, first, r0, prod, any_true);
+    else others_k<RPL, 7>(a, all, first, r0, prod, any_true);
   } else {
     const int4 e = ldc4(a.occx, q);
     const int codes[7] = {o.y, o.z, o.w, e.x, e.y, e.z, e.w};
