@@ -35,7 +35,7 @@ constexpr int kTargetBlocks = 2048;  // blocks per general-pass launch (256 CUs 
 // Workgroups of the LDS schedule up to which every restart gets its own
 // (two per CU of the 256).
 constexpr int64_t kPersistSpreadGroups = 512;
-constexpr int64_t kXseqChunks = 16384;
+constexpr int64_t kXseqChunks = 65536;
 constexpr int kSegDivSinglePass = 16;  // single-pass segment = one item's share / 16 (measured)
 constexpr int kClassShort = 0, kClassWave = 1;  // passes of the stored-clause classes
 constexpr int32_t kLocalWindow = 4096;
@@ -1156,9 +1156,10 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       }
       if (fvb[f + 1] > cb) { vc.beg.push_back(cb); vc.end.push_back(fvb[f + 1]); }
       // segment chunks of this formula: about one segment per item slot in
-      // the flat plan, so no slot walks several segments in a row and the
-      // hottest variables spread over the chip; about `target` cost each
-      // otherwise
+      // the flat plan and the single pass, so no slot walks several
+      // segments in a row and the hottest variables spread over the chip
+      // (and the variable chunks' size does not set theirs); about
+      // `target` cost each in the two-phase plan
       sc.f_first[f] = sc.count();
       const int32_t s_lo = heavy_sbeg[heavy_f_first[f]], s_hi = (int32_t)seg_var.size();
       // run order of the formula's segments (chunks cover runs of it).  In
@@ -1180,7 +1181,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
       }
       int32_t sb = s_lo;
       int64_t sacc = 0;
-      const int64_t seg_target = flat ? std::max<int64_t>(64, seg_cap * ipb) : target_f;
+      const int64_t seg_target = !two ? std::max<int64_t>(64, seg_cap * ipb) : target_f;
       for (int32_t i = s_lo; i < s_hi; ++i) {
         const int32_t sg = seg_perm[i];
         for (int32_t q = seg_q0[sg]; q < seg_q1[sg]; ++q) sacc += occ_cost[q];
