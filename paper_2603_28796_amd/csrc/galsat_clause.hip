@@ -507,8 +507,31 @@ __global__ __launch_bounds__(256) void k_pack_bits(const float* x, int32_t ldx, 
   }
 }
 
+// mask AND "literal false" over the literals [ps, pe) of one clause, W
+// literals a trip: their codes, then their bit-plane words, all loads in
+// flight (positions past the clause reread its last literal and are not
+// used).
+template <int W>
+__device__ __forceinline__ uint64_t and_literals_false(const int32_t* clause_lits,
+                                                       const uint64_t* bw, int ps, int pe,
+                                                       uint64_t mask) {
+  for (int p = ps; p < pe; p += W) {
+    int code[W];
+    uint64_t b[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) code[u] = clause_lits[min(p + u, pe - 1)];
+#pragma unroll
+    for (int u = 0; u < W; ++u) b[u] = bw[code[u] >> 1];
+#pragma unroll
+    for (int u = 0; u < W; ++u)
+      if (p + u < pe) mask &= (code[u] & 1) ? b[u] : ~b[u];
+  }
+  return mask;
+}
+
 // Lanes take one clause each; for the 64 restarts of word w a clause's
-// "unsatisfied" mask is the AND over its literals of "literal false".  The
+// "unsatisfied" mask is the AND over its literals of "literal false"
+// (eight literals a trip for clauses longer than 8, else four).  The
 // per-restart count over the wave's 64 clauses is then one ballot and one
 // popcount per restart, accumulated by the lane that owns the restart.
 // order: block -> chunk (-1: nothing), or null.
@@ -532,12 +555,11 @@ __global__ __launch_bounds__(256) void k_count_unsat(const int32_t* clause_ptr,
     uint64_t mask = 0;
     if (t < ce) {
       mask = valid;
-      for (int p = clause_ptr[t]; p < clause_ptr[t + 1]; ++p) {
-        const int code = clause_lits[p];
-        const uint64_t b = bw[code >> 1];
-        const uint64_t lit_is_true = (code & 1) ? ~b : b;
-        mask &= ~lit_is_true;
-      }
+      const int ps = clause_ptr[t], pe = clause_ptr[t + 1];
+      if (pe - ps > 8)
+        mask = and_literals_false<8>(clause_lits, bw, ps, pe, mask);
+      else
+        mask = and_literals_false<4>(clause_lits, bw, ps, pe, mask);
     }
     for (int j = 0; j < 64; ++j) {
       const uint64_t bal = __ballot((mask >> j) & 1ULL);
