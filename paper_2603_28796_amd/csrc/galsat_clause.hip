@@ -548,6 +548,7 @@ __global__ __launch_bounds__(256) void k_count_unsat(const int32_t* clause_ptr,
   const int cb = chunk_cbeg[chunk], ce = chunk_cend[chunk];
   const int rem = R - word * 64;
   const uint64_t valid = rem >= 64 ? ~0ULL : ((1ULL << rem) - 1ULL);
+  const int jmax = rem >= 64 ? 64 : rem;
   const uint64_t* bw = bits + (int64_t)word * n;
   int cnt = 0;
   for (int base = cb + wv * 64; base < ce; base += 256) {
@@ -561,7 +562,9 @@ __global__ __launch_bounds__(256) void k_count_unsat(const int32_t* clause_ptr,
       else
         mask = and_literals_false<4>(clause_lits, bw, ps, pe, mask);
     }
-    for (int j = 0; j < 64; ++j) {
+    // restarts past R have no bits (valid masks them), so their ballots
+    // are skipped: the loop runs over this word's restarts only
+    for (int j = 0; j < jmax; ++j) {
       const uint64_t bal = __ballot((mask >> j) & 1ULL);
       if (lane == j) cnt += __popcll(bal);
     }
