@@ -483,26 +483,36 @@ __global__ void k_zero_i32(int32_t* p, int64_t count) {
 
 // ------------------------------------------------------- round & count
 //
-// bits[w][v]: bit l = [x[v][64w + l] > 0.5] packed by one wavefront ballot.
-// A wave takes kPackU consecutive variables per trip, all their loads
-// issued before the ballots.
+// bits[w][v]: bit l = [x[v][64w + l] > 0.5] packed by wavefront ballots.
+// P lanes per variable (P = 64, or 32 / 16 when all restarts fit one word
+// and R <= P), so one ballot packs 64/P variables; a wave takes kPackU
+// ballots' worth of consecutive variables per trip, all loads first.
 constexpr int kPackU = 8;
 
+template <int P>
 __global__ __launch_bounds__(256) void k_pack_bits(const float* x, int32_t ldx, int32_t n,
                                                    int32_t R, uint64_t* bits) {
+  constexpr int VPB = 64 / P;  // variables per ballot
   const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int word = blockIdx.y;
-  const int r = word * 64 + lane;
-  for (int64_t v0 = ((int64_t)blockIdx.x * 4 + wv) * kPackU; v0 < n;
-       v0 += (int64_t)gridDim.x * 4 * kPackU) {
+  const int sub = lane / P, r = word * 64 + lane % P;
+  for (int64_t v0 = ((int64_t)blockIdx.x * 4 + wv) * kPackU * VPB; v0 < n;
+       v0 += (int64_t)gridDim.x * 4 * kPackU * VPB) {
     float val[kPackU];
 #pragma unroll
-    for (int u = 0; u < kPackU; ++u)
-      val[u] = (r < R && v0 + u < n) ? x[(v0 + u) * ldx + r] : 0.0f;
+    for (int u = 0; u < kPackU; ++u) {
+      const int64_t v = v0 + u * VPB + sub;
+      val[u] = (r < R && v < n) ? x[v * ldx + r] : 0.0f;
+    }
 #pragma unroll
     for (int u = 0; u < kPackU; ++u) {
       const uint64_t m = __ballot(val[u] > 0.5f);
-      if (lane == 0 && v0 + u < n) bits[(int64_t)word * n + v0 + u] = m;
+      const int64_t v = v0 + u * VPB + lane;  // lane k < VPB stores variable k's word
+      if (lane < VPB && v < n) {
+        uint64_t w = m;
+        if constexpr (P < 64) w = (m >> (lane * P)) & ((1ULL << P) - 1ULL);
+        bits[(int64_t)word * n + v] = w;
+      }
     }
   }
 }
@@ -760,8 +770,15 @@ hipError_t launch_zero_i32(int32_t* p, int64_t count, hipStream_t s) {
 hipError_t launch_pack_bits(const float* x, int32_t ldx, int32_t n, int32_t R, uint64_t* bits,
                             hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  dim3 grid(grid_x_for(((int64_t)n + 4 * kPackU - 1) / (4 * kPackU)), (R + 63) / 64), block(256);
-  hipLaunchKernelGGL(k_pack_bits, grid, block, 0, s, x, ldx, n, R, bits);
+  const int P = R <= 16 ? 16 : R <= 32 ? 32 : 64;
+  const int64_t per_block = 4 * kPackU * (64 / P);
+  dim3 grid(grid_x_for((n + per_block - 1) / per_block), (R + 63) / 64), block(256);
+  if (P == 16)
+    hipLaunchKernelGGL((k_pack_bits<16>), grid, block, 0, s, x, ldx, n, R, bits);
+  else if (P == 32)
+    hipLaunchKernelGGL((k_pack_bits<32>), grid, block, 0, s, x, ldx, n, R, bits);
+  else
+    hipLaunchKernelGGL((k_pack_bits<64>), grid, block, 0, s, x, ldx, n, R, bits);
   return hipGetLastError();
 }
 
