@@ -174,8 +174,10 @@ typedef struct {
                               of the next batch loaded during the current one's
                               gathers; on by default from 24 occurrences per variable),
                               rsort (1/0: a variable's clause-row records in row order,
-                              default 1) and sord (1/0: split-variable segments run in
-                              the order of the first clause row they read, default 1).
+                              default 1), sord (1/0: split-variable segments run in
+                              the order of the first clause row they read, default 1)
+                              and psort (1/0: a variable's pair records in the order
+                              of their nearer partner variable, default 1).
                               Keys left out take the plan's own choice. */
 } galsat_options;
 

@@ -407,11 +407,13 @@ galsat_status create_fail(galsat_status s, const std::string& msg) {
 // the next batch prefetched or not), rsort (flat plan: 1/0, a variable's
 // clause rows in row order or in slot order) and sord (flat plan: 1/0,
 // segments of split variables run in the order of the first clause row
-// they read, or variable by variable).
+// they read, or variable by variable) and psort (flat plan: 1/0, each
+// variable's pair records in the order of their nearer partner, or in slot
+// order).
 void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, int* xcdc,
                     int* stream_items, int* two_phase, int* dsort, int* csort, int* wave,
                     int* short_clauses, int* xseq, int* segdiv, int* ldsrg, int* ldsstage,
-                    int* ldslpt, int* xpin, int* flat, int* pf, int* rsort, int* sord) {
+                    int* ldslpt, int* xpin, int* flat, int* pf, int* rsort, int* sord, int* psort) {
   if (!spec) return;
   std::string s(spec);
   size_t pos = 0;
@@ -442,6 +444,7 @@ void apply_override(const char* spec, int* lpi, int* rpl, int* krec, int* tg, in
       else if (k == "xpin") *xpin = v;
       else if (k == "flat") *flat = v;
       else if (k == "sord") *sord = v;
+      else if (k == "psort") *psort = v;
       else if (k == "pf") *pf = v;
       else if (k == "rsort") *rsort = v;
     }
@@ -627,10 +630,10 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   int lpi_o = 0, rpl_o = 0, krec_o = -1, tg_o = 0, xcdc_o = -1, stream_o = -1, two_o = -1;
   int dsort_o = -1, csort_o = -1, wave_o = -1, short_o = -1, xseq_o = -1, segdiv_o = -1;
   int ldsrg_o = 0, ldsstage_o = -1, ldslpt_o = -1, xpin_o = -1, flat_o = -1, pf_o = -1, rsort_o = -1;
-  int sord_o = -1;
+  int sord_o = -1, psort_o = -1;
   apply_override(opt.plan_override, &lpi_o, &rpl_o, &krec_o, &tg_o, &xcdc_o, &stream_o, &two_o,
                  &dsort_o, &csort_o, &wave_o, &short_o, &xseq_o, &segdiv_o, &ldsrg_o, &ldsstage_o,
-                 &ldslpt_o, &xpin_o, &flat_o, &pf_o, &rsort_o, &sord_o);
+                 &ldslpt_o, &xpin_o, &flat_o, &pf_o, &rsort_o, &sord_o, &psort_o);
   const bool csort = csort_o != 0;
   // Persistent LDS schedule: every formula's restart group must fit in LDS
   // (state double-buffered); SGD only; every clause recomputed.
@@ -882,6 +885,7 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
   std::vector<int2> pairs;
   std::vector<uint32_t> lrec;
   const bool rsort = rsort_o != 0;
+  const bool psort = psort_o != 0;
   // Prefetching the next batch's records pays when a variable's record runs
   // span several batches (measured: +7 % at 38 occurrences per variable,
   // -13 % at 14), so by default from 24 occurrences per variable on.
@@ -973,6 +977,23 @@ extern "C" galsat_status galsat_create(const galsat_problem* prob, const galsat_
           } else {
             lrec[(size_t)b++] = (uint32_t)(row_of[t] - f_rbeg[var_formula[v]]) | own_neg;
           }
+        }
+        // psort: within each of the variable's three pair runs (first
+        // literal positive, first literal negated, the others), the nearer
+        // partner first in each record (a product of two factors does not
+        // depend on their order) and the records in that partner's order,
+        // so a hot variable's pair gathers sweep the state rows in order
+        if (psort) {
+          auto near_first = [](int2 r) {
+            const uint32_t sgn = (uint32_t)r.x & 0x80000000u;
+            const int32_t a1 = r.x & 0x7fffffff, a2 = r.y;
+            return (a2 >> 1) < (a1 >> 1) ? make_int2((int32_t)((uint32_t)a2 | sgn), a1) : r;
+          };
+          const int64_t runs[4] = {pair_first[v], pair_fneg[v], pair_mid[v], pair_first[v + 1]};
+          for (int64_t i = runs[0]; i < runs[3]; ++i) pairs[(size_t)i] = near_first(pairs[(size_t)i]);
+          for (int k = 0; k < 3; ++k)
+            std::stable_sort(pairs.begin() + runs[k], pairs.begin() + runs[k + 1],
+                             [](int2 p1, int2 p2) { return (p1.x & 0x7fffffff) < (p2.x & 0x7fffffff); });
         }
         // a variable's clause rows: positive own literals first, then
         // negated ones (one partial sign per run), each in row order, so a
