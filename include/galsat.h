@@ -79,8 +79,11 @@ typedef struct galsat_ctx* galsat_handle;
  *   var_occ [L]       for variable v, the positions p of clause_lits with
  *                     clause_lits[p] >> 1 == v: exactly the transpose of the
  *                     clause-major CSR, every position exactly once.  The
- *                     order inside a variable is the order in which its
- *                     gradient contributions are summed.
+ *                     order inside a variable is the order in which the
+ *                     single-pass and two-phase plans sum its gradient
+ *                     contributions; the flat plan sums them in its own
+ *                     fixed order (first-literal pairs, the other pairs,
+ *                     then clause rows).
  * All arrays are int32; L < 2^31.  With inputs_on_device = 0 they are host
  * pointers, with 1 device pointers.  galsat_create copies them: the caller
  * may free or reuse them as soon as it returns.
